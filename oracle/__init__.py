@@ -1,0 +1,289 @@
+"""ctypes front end of the CPU oracle (oracle/liboracle.so).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the plain FP64 reference the HIP
+path is checked against.  Only the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import it; the product package never does.
+
+Arrays are numpy float64 in the layout u[v, element, node] flattened, see
+``esrk_oracle.h``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+SSPRK33 = 0
+RK44 = 1
+
+ENOROOT = -4
+ENONPHYS = -5
+
+
+class Mesh(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int),
+        ("deg", C.c_int),
+        ("nel", C.c_int * 3),
+        ("lo", C.c_double * 3),
+        ("hi", C.c_double * 3),
+        ("gas_gamma", C.c_double),
+        ("gas_r", C.c_double),
+        ("mu", C.c_double),
+        ("prandtl", C.c_double),
+        ("lambda_scale", C.c_double),
+        ("volume_flux", C.c_int),
+    ]
+
+
+class RelaxOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("gamma_max", C.c_double), ("maxit", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from oracle import build as _b
+            _b.build()
+        L = C.CDLL(_LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        mp = C.POINTER(Mesh)
+        L.orc_lgl.argtypes = [C.c_int, dp, dp]
+        L.orc_dmat.argtypes = [C.c_int, dp]
+        L.orc_logmean.argtypes = [C.c_double, C.c_double]
+        L.orc_logmean.restype = C.c_double
+        L.orc_entropy.argtypes = [C.c_int, C.c_double, dp]
+        L.orc_entropy.restype = C.c_double
+        L.orc_entropy_vars.argtypes = [C.c_int, C.c_double, dp, dp]
+        L.orc_phys_flux.argtypes = [C.c_int, C.c_double, C.c_int, dp, dp]
+        L.orc_ec_flux.argtypes = [C.c_int, C.c_double, C.c_int, dp, dp, dp]
+        L.orc_wave_speed.argtypes = [C.c_int, C.c_double, dp]
+        L.orc_wave_speed.restype = C.c_double
+        L.orc_num_elems.argtypes = [mp]
+        L.orc_num_elems.restype = C.c_long
+        L.orc_num_nodes.argtypes = [mp]
+        L.orc_num_nodes.restype = C.c_long
+        L.orc_rhs.argtypes = [mp, dp, dp, dp, dp]
+        L.orc_volume_term.argtypes = [mp, dp, dp]
+        L.orc_interface_dissipation.argtypes = [mp, dp]
+        L.orc_interface_dissipation.restype = C.c_double
+        L.orc_br1_gradient.argtypes = [mp, dp, dp]
+        L.orc_elem_entropy.argtypes = [mp, dp, dp]
+        L.orc_cfl_dt.argtypes = [mp, dp, C.c_double]
+        L.orc_cfl_dt.restype = C.c_double
+        L.orc_tableau_stages.argtypes = [C.c_int]
+        L.orc_rk_step.argtypes = [mp, C.c_int, dp, C.c_double, dp, dp, dp, dp, dp]
+        L.orc_local_relaxation_solve.argtypes = [
+            mp, C.POINTER(RelaxOpts), dp, dp, dp, dp, dp, dp, dp, dp,
+            C.POINTER(C.c_int), C.POINTER(C.c_long)]
+        L.orc_relax_r.argtypes = [mp, C.c_long, dp, dp, C.c_double, C.c_double,
+                                  C.POINTER(C.c_int)]
+        L.orc_relax_r.restype = C.c_longdouble
+        L.orc_step.argtypes = [mp, C.c_int, C.POINTER(RelaxOpts), C.c_double, C.c_double,
+                               dp, dp, dp, dp, dp, C.POINTER(C.c_long)]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def mesh(dim, deg, nel, lo, hi, gas_gamma=1.4, gas_r=1.0, mu=0.0, prandtl=0.72,
+         lambda_scale=1.0, volume_flux=0) -> Mesh:
+    m = Mesh()
+    m.dim, m.deg = dim, deg
+    nel = list(nel) + [1] * (3 - len(nel))
+    lo = list(lo) + [0.0] * (3 - len(lo))
+    hi = list(hi) + [1.0] * (3 - len(hi))
+    for q in range(3):
+        m.nel[q], m.lo[q], m.hi[q] = nel[q], lo[q], hi[q]
+    m.gas_gamma, m.gas_r, m.mu, m.prandtl = gas_gamma, gas_r, mu, prandtl
+    m.lambda_scale, m.volume_flux = lambda_scale, volume_flux
+    return m
+
+
+def relax_opts(tol=1e-15, gamma_max=4.0, maxit=200) -> RelaxOpts:
+    o = RelaxOpts()
+    o.tol, o.gamma_max, o.maxit = tol, gamma_max, maxit
+    return o
+
+
+def sizes(m: Mesh):
+    return int(lib().orc_num_elems(C.byref(m))), int(lib().orc_num_nodes(C.byref(m)))
+
+
+def lgl(deg):
+    x = np.zeros(deg + 1)
+    w = np.zeros(deg + 1)
+    assert lib().orc_lgl(deg, _p(x), _p(w)) == 0
+    return x, w
+
+
+def dmat(deg):
+    D = np.zeros((deg + 1) * (deg + 1))
+    assert lib().orc_dmat(deg, _p(D)) == 0
+    return D.reshape(deg + 1, deg + 1)
+
+
+def logmean(a, b):
+    return lib().orc_logmean(float(a), float(b))
+
+
+def entropy(dim, gg, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return lib().orc_entropy(dim, gg, _p(u))
+
+
+def entropy_vars(dim, gg, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    w = np.zeros(dim + 2)
+    lib().orc_entropy_vars(dim, gg, _p(u), _p(w))
+    return w
+
+
+def phys_flux(dim, gg, m, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    f = np.zeros(dim + 2)
+    lib().orc_phys_flux(dim, gg, m, _p(u), _p(f))
+    return f
+
+
+def ec_flux(dim, gg, m, uL, uR):
+    uL = np.ascontiguousarray(uL, dtype=np.float64)
+    uR = np.ascontiguousarray(uR, dtype=np.float64)
+    f = np.zeros(dim + 2)
+    lib().orc_ec_flux(dim, gg, m, _p(uL), _p(uR), _p(f))
+    return f
+
+
+def wave_speed(dim, gg, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return lib().orc_wave_speed(dim, gg, _p(u))
+
+
+def rhs(m: Mesh, u, want_visc=False):
+    ne, N = sizes(m)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    dudt = np.zeros_like(u)
+    er = np.zeros(ne)
+    vd = np.zeros(ne)
+    rc = lib().orc_rhs(C.byref(m), _p(u), _p(dudt), _p(er), _p(vd))
+    if rc != 0:
+        raise RuntimeError(f"orc_rhs failed: {rc}")
+    if want_visc:
+        return dudt, er, vd
+    return dudt, er
+
+
+def volume_term(m: Mesh, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    V = np.zeros_like(u)
+    assert lib().orc_volume_term(C.byref(m), _p(u), _p(V)) == 0
+    return V
+
+
+def interface_dissipation(m: Mesh, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return lib().orc_interface_dissipation(C.byref(m), _p(u))
+
+
+def br1_gradient(m: Mesh, u):
+    ne, N = sizes(m)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    th = np.zeros(m.dim * (m.dim + 2) * N)
+    assert lib().orc_br1_gradient(C.byref(m), _p(u), _p(th)) == 0
+    return th
+
+
+def elem_entropy(m: Mesh, u):
+    ne, N = sizes(m)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    eta = np.zeros(ne)
+    assert lib().orc_elem_entropy(C.byref(m), _p(u), _p(eta)) == 0
+    return eta
+
+
+def cfl_dt(m: Mesh, u, cfl):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return lib().orc_cfl_dt(C.byref(m), _p(u), cfl)
+
+
+def tableau_stages(tab):
+    return int(lib().orc_tableau_stages(tab))
+
+
+def rk_step(m: Mesh, tab, u_old, dt, want_stages=False):
+    ne, N = sizes(m)
+    s = tableau_stages(tab)
+    u_old = np.ascontiguousarray(u_old, dtype=np.float64)
+    du = np.zeros_like(u_old)
+    deta = np.zeros(ne)
+    ys = np.zeros((s,) + u_old.shape) if want_stages else None
+    ks = np.zeros((s,) + u_old.shape) if want_stages else None
+    es = np.zeros((s, ne)) if want_stages else None
+    rc = lib().orc_rk_step(C.byref(m), tab, _p(u_old), float(dt), _p(du), _p(deta),
+                           _p(ys), _p(ks), _p(es))
+    if rc != 0:
+        raise RuntimeError(f"orc_rk_step failed: {rc}")
+    if want_stages:
+        return du, deta, ys, ks, es
+    return du, deta
+
+
+def local_relaxation_solve(m: Mesh, u_old, du, deta, opts: RelaxOpts | None = None):
+    """Returns dict(gamma, gamma_k, phi0, curv, noise, iters, rc, bad_elem)."""
+    ne, N = sizes(m)
+    opts = opts or relax_opts()
+    u_old = np.ascontiguousarray(u_old, dtype=np.float64)
+    du = np.ascontiguousarray(du, dtype=np.float64)
+    deta = np.ascontiguousarray(deta, dtype=np.float64)
+    gk = np.zeros(ne)
+    phi0 = np.zeros(ne)
+    curv = np.zeros(ne)
+    noise = np.zeros(ne)
+    iters = np.zeros(ne, dtype=np.int32)
+    gam = C.c_double(0.0)
+    bad = C.c_long(-1)
+    rc = lib().orc_local_relaxation_solve(
+        C.byref(m), C.byref(opts), _p(u_old), _p(du), _p(deta), _p(gk), C.byref(gam),
+        _p(phi0), _p(curv), _p(noise), iters.ctypes.data_as(C.POINTER(C.c_int)),
+        C.byref(bad))
+    return dict(gamma=gam.value, gamma_k=gk, phi0=phi0, curv=curv, noise=noise,
+                iters=iters, rc=rc, bad_elem=bad.value)
+
+
+def relax_r(m: Mesh, k, u_old, du, deta_k, gamma):
+    ok = C.c_int(1)
+    u_old = np.ascontiguousarray(u_old, dtype=np.float64)
+    du = np.ascontiguousarray(du, dtype=np.float64)
+    r = lib().orc_relax_r(C.byref(m), k, _p(u_old), _p(du), float(deta_k), float(gamma),
+                          C.byref(ok))
+    return float(r), bool(ok.value)
+
+
+def step(m: Mesh, tab, u, t, cfl=0.5, dt=0.0, opts: RelaxOpts | None = None):
+    """In-place on u (numpy).  Returns dict(t, gamma, gamma_k, dt, rc, bad_elem)."""
+    ne, N = sizes(m)
+    opts = opts or relax_opts()
+    assert u.dtype == np.float64 and u.flags["C_CONTIGUOUS"]
+    tt = C.c_double(t)
+    gam = C.c_double(0.0)
+    dtu = C.c_double(0.0)
+    gk = np.zeros(ne)
+    bad = C.c_long(-1)
+    rc = lib().orc_step(C.byref(m), tab, C.byref(opts), float(cfl), float(dt), _p(u),
+                        C.byref(tt), C.byref(gam), _p(gk), C.byref(dtu), C.byref(bad))
+    return dict(t=tt.value, gamma=gam.value, gamma_k=gk, dt=dtu.value, rc=rc,
+                bad_elem=bad.value)
