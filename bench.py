@@ -1,0 +1,189 @@
+"""Throughput of the locally entropy-stable relaxation RK hot path on one GPU.
+
+Workload: 3-D compressible Euler Taylor-Green vortex, Mach 0.1, periodic
+[0, 2 pi]^3, 16^3 elements of degree 3 (262,144 Lobatto nodes, 5 fields),
+entropy-conservative flux differencing with local Lax-Friedrichs interfaces,
+RK(4,4) at CFL 0.5 with local relaxation every step.  One timed "step" is one
+whole locally relaxed RK(4,4) step (4 right-hand sides + stage updates, the
+per-element relaxation solve, the global gamma and the relaxed update), with
+the CFL step size computed on the device.
+
+Metric: DOF-stage updates per second = nodes x RK stages / wall time of the
+step loop (inputs resident in HBM; no host synchronization inside the loop).
+The headline value is the FP64 path; the FP32-flux / FP64-relaxation path is
+reported beside it.  The CPU baseline is the FP64 oracle on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+NEL, DEG, MACH = 16, 3, 0.1
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+# Algorithmic FP64 work of one launch of the fused stage kernel (3-D):
+# 90 flop per unordered volume node pair, 130 flop per interface node pair,
+# 80 flop per node (primitives, logarithms, entropy variables, stage update).
+FLOP_PAIR, FLOP_FACE, FLOP_NODE = 90.0, 130.0, 80.0
+# Algorithmic HBM bytes of one middle-stage launch per node (FP64, 5 fields):
+# read y, u_old, du; write du, y_next.
+BYTES_NODE_STAGE = 5 * 5 * 8
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-steps", type=int, default=3)
+    p.add_argument("--kernel-reps", type=int, default=50)
+    return p.parse_args()
+
+
+def run_mode(esrk, I, torch, precision, steps, warmup):
+    ms = I.tgv_mesh(NEL, DEG)
+    cfg = esrk.make_config(ms.dim, ms.deg, ms.nel, ms.lo, ms.hi, gas_gamma=ms.gas_gamma,
+                           precision=precision, tableau=esrk.RK44, cfl=0.5)
+    ctx = esrk.Context(cfg)
+    u = torch.as_tensor(I.tgv_state(ms, MACH)).to("cuda")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        ctx.step(u, t, 0.0, None, stats)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        ctx.step(u, t, 0.0, None, stats)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = e0.elapsed_time(e1)
+    rc, bad = ctx.sync_status()
+    if rc != 0:
+        raise RuntimeError(f"device status {esrk.STATUS.get(rc)} at element {bad}")
+    st = stats.cpu().numpy()
+    return ctx, u, dict(ms_total=ms_total, wall_s=wall, N=ctx.N, gamma=float(st[0]),
+                        dt=float(st[1]), t=float(st[2]))
+
+
+def time_stage_kernel(esrk, torch, ctx, u, reps):
+    """Average duration of one fused stage-kernel launch (middle RK stage),
+    HIP events on the launch stream (the default stream)."""
+    n = u.numel()
+    ya = torch.empty(n, dtype=torch.float64, device="cuda")
+    du = torch.zeros(n, dtype=torch.float64, device="cuda")
+    deta = torch.zeros(ctx.ne, dtype=torch.float64, device="cuda")
+    dt = 1e-3
+    ctx.rk_stage(0, dt, u, u, ya, du, deta)
+    for _ in range(3):
+        ctx.rk_stage(1, dt, u, u, ya, du, deta)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.rk_stage(1, dt, u, u, ya, du, deta)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(I, steps):
+    import oracle as O
+    ms = I.tgv_mesh(NEL, DEG)
+    m = O.mesh(ms.dim, ms.deg, ms.nel, ms.lo, ms.hi, gas_gamma=ms.gas_gamma)
+    u = I.tgv_state(ms, MACH)
+    t = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = O.step(m, O.RK44, u, t, cfl=0.5)
+        t = r["t"]
+    el = time.perf_counter() - t0
+    stages = 4 * steps
+    return dict(value=ms.N * stages / el, unit="DOF-stage updates/s", cores=1, kind="oracle",
+                sample=f"{steps} locally relaxed RK(4,4) steps ({stages} stages) of the "
+                       f"16^3 p=3 TGV, {ms.N} nodes, single thread, {el:.1f} s")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no HIP device visible"}))
+        sys.exit(1)
+    from paper_2003_08831_amd import esrk
+    from paper_2003_08831_amd import inputs as I
+
+    ctx64, u64, r64 = run_mode(esrk, I, torch, esrk.FP64, a.steps, a.warmup)
+    ctx32, u32, r32 = run_mode(esrk, I, torch, esrk.FP32_FLUX, a.steps, a.warmup)
+    N = r64["N"]
+    stages = 4 * a.steps
+    val64 = N * stages / (r64["ms_total"] * 1e-3)
+    val32 = N * stages / (r32["ms_total"] * 1e-3)
+
+    kms = time_stage_kernel(esrk, torch, ctx64, u64, a.kernel_reps)
+    ne = ctx64.ne
+    n = DEG + 1
+    pairs = ne * 3 * n * n * (n * (n - 1) // 2)
+    faces = ne * 3 * n * n
+    flop = pairs * FLOP_PAIR + faces * FLOP_FACE + N * FLOP_NODE
+    tflops = flop / (kms * 1e-3) / 1e12
+    gbs = N * BYTES_NODE_STAGE / (kms * 1e-3) / 1e9
+    alu_frac = tflops / FP64_VECTOR_PEAK_TFLOPS
+    hbm_frac = gbs / HBM_PEAK_GBS
+    if alu_frac >= hbm_frac:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": None}
+    roof.update({"kernel": "rhs_kernel<3,4,double> (fused RK stage)",
+                 "kernel_ms": round(kms, 4),
+                 "other": {"hbm_GBs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4),
+                           "fp64_TFLOPs": round(tflops, 3), "alu_frac": round(alu_frac, 4)}})
+
+    out = {
+        "metric": "DOF-stage updates/s incl. local relaxation, FP32-mixed vs FP64, 1 MI355X",
+        "value": round(val64, 1),
+        "unit": "DOF-stage updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(r64["ms_total"] / a.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (analytic Taylor-Green initial state)",
+        "config": {"workload": "3-D Euler Taylor-Green vortex, Mach 0.1, 16^3 elements, "
+                               "degree 3 (262144 nodes), EC flux differencing + LLF, "
+                               "RK(4,4) CFL 0.5, local relaxation",
+                   "nodes": N, "stages_timed": stages, "precision": "fp64"},
+        "fp32_flux": {"value": round(val32, 1), "ms_per_step": round(r32["ms_total"] / a.steps, 4),
+                      "dtype": "f32 flux / f64 relaxation+state", "speedup_vs_fp64":
+                      round(val32 / val64, 3)},
+        "run": {"gamma_last": r64["gamma"], "dt_last": r64["dt"], "t_end": r64["t"]},
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(I, a.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * esrk.h -- C-ABI of the MI355X (gfx950) locally entropy-stable relaxation
+ * Runge-Kutta hot path (Ranocha, Dalcin, Parsani, "Fully-Discrete Explicit
+ * Locally Entropy-Stable Schemes for the Compressible Euler and Navier-Stokes
+ * Equations", arXiv:2003.08831).
+ *
+ * The problem is the ODE u' = f(u) of Sec. 1, with f the entropy-stable
+ * semidiscretization of Sec. 3.1 (element equation: flux-differencing volume
+ * term with an entropy-conservative two-point flux on tensor-product Lobatto
+ * nodes, interface SATs with local Lax-Friedrichs dissipation and, for
+ * Navier-Stokes, BR1 viscous terms), advanced by an explicit Runge-Kutta
+ * method (Sec. 2, Runge-Kutta example) and made locally entropy stable by the
+ * local relaxation of Sec. 2 (local relaxation equation; theorem with
+ * gamma = min_k gamma_k).
+ *
+ * Conventions for every call:
+ *  - all array arguments are DEVICE pointers (HIP device memory, e.g. from
+ *    torch.empty(..., device="cuda")) owned by the caller; the library never
+ *    frees or retains them beyond the call;
+ *  - state layout: double u[v * N + k * nd + i], v in [0, dim+2) for
+ *    rho, rho*v_1..rho*v_dim, rho*E; element k lexicographic with x fastest;
+ *    node i lexicographic over (deg+1)^dim with xi_1 fastest;
+ *    nd = (deg+1)^dim, N = num_elems * nd;
+ *  - per-element arrays have num_elems entries;
+ *  - `stream` is a hipStream_t (NULL = the default stream); calls only
+ *    enqueue work on it and never synchronize the host, except
+ *    esrk_sync_status;
+ *  - argument errors are returned synchronously; conditions detected on the
+ *    device (no relaxation root, non-physical state) are latched in a device
+ *    status word and reported by esrk_sync_status;
+ *  - a context is not thread-safe; calls on one context must not overlap.
+ *  - the mesh is a periodic Cartesian box; every element has the same
+ *    polynomial degree.
+ */
+#ifndef ESRK_H
+#define ESRK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ESRK_OK = 0,
+  ESRK_EINVAL = 1,   /* bad argument or configuration */
+  ESRK_EHIP = 2,     /* a HIP runtime call failed */
+  ESRK_ENOMEM = 3,   /* workspace allocation failed */
+  ESRK_ENOROOT = 4,  /* an active element has no positive relaxation root */
+  ESRK_ENONPHYS = 5, /* rho <= 0 or p <= 0 in a state */
+  ESRK_ENAN = 6,     /* a NaN was produced */
+  ESRK_ENOTSUP = 7   /* configuration not compiled in */
+} esrk_status;
+
+enum { ESRK_FP64 = 0, ESRK_FP32_FLUX = 1 };
+enum { ESRK_SSPRK33 = 0, ESRK_RK44 = 1 };
+
+typedef struct {
+  int dim;             /* 1, 2 or 3 */
+  int deg;             /* polynomial degree p in [1, 5]; p+1 Lobatto nodes per direction */
+  int nel[3];          /* elements per direction (entries >= dim ignored) */
+  double lo[3], hi[3]; /* periodic box */
+  double gas_gamma;    /* ratio of specific heats */
+  double gas_r;        /* gas constant in p = rho R T */
+  double mu;           /* constant dynamic viscosity (0: Euler) */
+  double prandtl;      /* Prandtl number */
+  double lambda_scale; /* interface dissipation: 1 = local Lax-Friedrichs, 0 = EC surface */
+  int precision;       /* ESRK_FP64, or ESRK_FP32_FLUX (flux differencing in FP32) */
+  int tableau;         /* ESRK_SSPRK33 or ESRK_RK44 (both have b_i >= 0) */
+  double cfl;          /* dt = cfl * min h / ((deg+1) * max_i sum_m (|v_m| + c)) */
+  double root_tol;     /* relaxation bracket width, relative to max(1, gamma) */
+  int root_maxit;      /* iteration cap of the per-element root solve */
+  double gamma_max;    /* largest relaxation parameter tried */
+} esrk_config;
+
+typedef struct esrk_ctx esrk_ctx;
+
+/* Creates a context: validates cfg, builds the Lobatto SBP tables and
+ * allocates all device workspace (the only allocation the library makes).
+ * Sec. 3.1 (diagonal-norm SBP operators on Lobatto nodes). */
+esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out);
+void esrk_destroy(esrk_ctx* ctx);
+
+size_t esrk_num_nodes(const esrk_ctx* ctx);
+size_t esrk_num_elems(const esrk_ctx* ctx);
+int esrk_num_vars(const esrk_ctx* ctx);
+
+/* dudt = f(u) for the Euler equations (Sec. 3.1, element equation without
+ * the viscous terms).  eta_rate (nullable, [num_elems]):
+ * eta_rate[k] = sum_i M_i w(u_i).dudt_i, the element entropy rate that enters
+ * the estimate of Sec. 2 (Runge-Kutta example).  u and dudt must not alias. */
+esrk_status esrk_rhs_euler(esrk_ctx* ctx, const double* u, double* dudt,
+                           double* eta_rate, void* stream);
+
+/* dudt = f(u) for Navier-Stokes (Euler part plus BR1 viscous terms with
+ * mu > 0).  visc_diss (nullable): sum_i M_i sum_m theta_m,i . g_m,i >= 0.
+ * Returns ESRK_ENOTSUP while the viscous kernels are not compiled in. */
+esrk_status esrk_rhs_ns(esrk_ctx* ctx, const double* u, double* dudt, double* eta_rate,
+                        double* visc_diss, void* stream);
+
+/* One stage of the configured Runge-Kutta method (Sec. 2, stage equations and
+ * estimate), stage in [0, s):
+ *   k = f(y_in);
+ *   du  = (stage == 0 ? 0 : du) + dt b_stage k          (u_new - u_old after the last stage)
+ *   deta[k] = (stage == 0 ? 0 : deta[k]) + dt b_stage sum_i M_i w(y_in).k
+ *   y_out = y^{stage+1} (omitted after the last stage; y_out may be NULL there).
+ * For stage 0, y_in must equal u_old.  y_out must not alias y_in or u_old. */
+esrk_status esrk_rk_stage(esrk_ctx* ctx, int stage, double dt, const double* u_old,
+                          const double* y_in, double* y_out, double* du, double* deta,
+                          void* stream);
+
+/* Local relaxation (Sec. 2, local relaxation equation and theorem).  With the
+ * increments du = u_new - u_old and deta = eta_new - eta_old (eta_old is
+ * eta_k(u_old) for Runge-Kutta), gamma_k is the positive root of
+ *   phi_k(g) = (eta_k(u_old + g du) - eta_k(u_old) - g deta_k) / g,
+ * solved per element to root_tol; elements whose root is not determinable in
+ * FP64 (no curvature above round-off) get +INF.  *gamma (device scalar) =
+ * min_k gamma_k, or 1 if every element is inactive.  gamma_guess (nullable,
+ * float [num_elems]) seeds the solve; the result does not depend on it beyond
+ * root_tol.  iters (nullable, [num_elems]) receives the number of phi
+ * evaluations per element. */
+esrk_status esrk_local_relaxation_solve(esrk_ctx* ctx, const double* u_old,
+                                        const double* du, const double* deta,
+                                        const float* gamma_guess, double* gamma_k,
+                                        double* gamma, int32_t* iters, void* stream);
+
+/* One whole locally relaxed step, in place on u (Sec. 2: RK step, estimate,
+ * gamma = min_k gamma_k, u <- u + gamma du, t <- t + gamma dt).  t is a device
+ * scalar.  dt > 0 is used as given; dt <= 0 takes dt from the CFL rule on the
+ * device.  gamma_k_out (nullable, [num_elems]) and stats_out (nullable, device
+ * double[4] = {gamma, dt, t, number of inactive elements}) are written on the
+ * device.  If the device detects an error, u and t are left unchanged and the
+ * status is latched.  No host synchronization, no allocation. */
+esrk_status esrk_step(esrk_ctx* ctx, double* u, double* t, double dt, double* gamma_k_out,
+                      double* stats_out, void* stream);
+
+/* Synchronizes `ctx`'s work on the stream of its last call, returns and clears
+ * the latched device status; *bad_elem (nullable) receives the smallest
+ * offending element index or -1. */
+esrk_status esrk_sync_status(esrk_ctx* ctx, int64_t* bad_elem);
+
+const char* esrk_status_str(esrk_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

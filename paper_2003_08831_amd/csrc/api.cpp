@@ -1,0 +1,316 @@
+// Host side of the C-ABI (include/esrk.h): context, workspace and the
+// enqueue-only entry points.  Every step of the path runs in the HIP kernels
+// of rhs.hip and relax.hip; this file only validates, sizes and launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using esrk::DevScalars;
+using esrk::MeshParams;
+using esrk::StageCoef;
+
+struct esrk_ctx {
+  esrk_config cfg;
+  MeshParams mp;
+  int stages;
+  StageCoef sc[4];
+  size_t N, ne;
+  int nv;
+  double* ya = nullptr;
+  double* yb = nullptr;
+  double* du = nullptr;
+  double* deta = nullptr;
+  double* gamma_k = nullptr;
+  int32_t* iters = nullptr;
+  double* speed_parts = nullptr;
+  esrk::RelaxPart* relax_parts = nullptr;
+  int n_relax_parts = 0;
+  DevScalars* scal = nullptr;
+  hipStream_t last = nullptr;
+};
+
+namespace {
+
+// Runge-Kutta methods in the device's two-register form
+//   y_{i+1} = alpha u_old + beta y_i + c dt k_i,  du += b dt k_i.
+// SSPRK(3,3): y2 = u + dt k1, y3 = 3/4 u + 1/4 y2 + 1/4 dt k2, b = (1/6, 1/6, 2/3).
+// RK(4,4): y_{i+1} = u + c_{i+1} dt k_i with c = (1/2, 1/2, 1), b = (1/6, 1/3, 1/3, 1/6).
+int tableau_coefs(int which, StageCoef* sc) {
+  if (which == ESRK_SSPRK33) {
+    sc[0] = {1.0, 0.0, 1.0, 1.0 / 6.0};
+    sc[1] = {0.75, 0.25, 0.25, 1.0 / 6.0};
+    sc[2] = {0.0, 0.0, 0.0, 2.0 / 3.0};
+    return 3;
+  }
+  if (which == ESRK_RK44) {
+    sc[0] = {1.0, 0.0, 0.5, 1.0 / 6.0};
+    sc[1] = {1.0, 0.0, 0.5, 1.0 / 3.0};
+    sc[2] = {1.0, 0.0, 1.0, 1.0 / 3.0};
+    sc[3] = {0.0, 0.0, 0.0, 1.0 / 6.0};
+    return 4;
+  }
+  return 0;
+}
+
+esrk_status hip_status(hipError_t e) { return e == hipSuccess ? ESRK_OK : ESRK_EHIP; }
+
+esrk::RhsArgs base_args(esrk_ctx* c) {
+  esrk::RhsArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.scal = c->scal;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* esrk_status_str(esrk_status s) {
+  switch (s) {
+    case ESRK_OK: return "ok";
+    case ESRK_EINVAL: return "invalid argument";
+    case ESRK_EHIP: return "HIP runtime error";
+    case ESRK_ENOMEM: return "out of device memory";
+    case ESRK_ENOROOT: return "no positive relaxation root in an active element";
+    case ESRK_ENONPHYS: return "non-physical state (rho <= 0 or p <= 0)";
+    case ESRK_ENAN: return "NaN produced";
+    case ESRK_ENOTSUP: return "configuration not supported";
+  }
+  return "unknown status";
+}
+
+esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
+  if (!cfg || !out) return ESRK_EINVAL;
+  *out = nullptr;
+  const esrk_config& c = *cfg;
+  if (c.dim < 1 || c.dim > 3 || c.deg < 1 || c.deg > esrk::kMaxN - 1) return ESRK_EINVAL;
+  if (!(c.gas_gamma > 1.0) || !(c.gas_r > 0.0) || c.mu < 0.0) return ESRK_EINVAL;
+  if (c.precision != ESRK_FP64 && c.precision != ESRK_FP32_FLUX) return ESRK_EINVAL;
+  if (c.tableau != ESRK_SSPRK33 && c.tableau != ESRK_RK44) return ESRK_ENOTSUP;
+  if (c.mu > 0.0 && !(c.prandtl > 0.0)) return ESRK_EINVAL;
+  size_t ne = 1;
+  for (int m = 0; m < c.dim; ++m) {
+    if (c.nel[m] < 1 || !(c.hi[m] > c.lo[m])) return ESRK_EINVAL;
+    ne *= (size_t)c.nel[m];
+  }
+  if (ne > (size_t)INT32_MAX) return ESRK_EINVAL;
+  esrk_ctx* x = new (std::nothrow) esrk_ctx();
+  if (!x) return ESRK_ENOMEM;
+  x->cfg = c;
+  if (!(x->cfg.root_tol > 0.0)) x->cfg.root_tol = 1e-12;
+  if (x->cfg.root_maxit <= 0) x->cfg.root_maxit = 60;
+  if (!(x->cfg.gamma_max > 1.0)) x->cfg.gamma_max = 4.0;
+  if (!(x->cfg.cfl > 0.0)) x->cfg.cfl = 0.5;
+  MeshParams& mp = x->mp;
+  std::memset(&mp, 0, sizeof(mp));
+  mp.dim = c.dim;
+  mp.n = c.deg + 1;
+  mp.nd = 1;
+  for (int m = 0; m < c.dim; ++m) mp.nd *= mp.n;
+  mp.ne = (int)ne;
+  double hmin = INFINITY;
+  for (int m = 0; m < 3; ++m) {
+    mp.nel[m] = m < c.dim ? c.nel[m] : 1;
+    const double h = m < c.dim ? (c.hi[m] - c.lo[m]) / c.nel[m] : 1.0;
+    mp.two_over_h[m] = 2.0 / h;
+    mp.half_h[m] = 0.5 * h;
+    if (m < c.dim) hmin = std::fmin(hmin, h);
+  }
+  double xs[esrk::kMaxN], D[esrk::kMaxN * esrk::kMaxN];
+  esrk::lobatto_tables(c.deg, xs, mp.w, D);
+  for (int i = 0; i < mp.n * mp.n; ++i) mp.D2[i] = 2.0 * D[i];
+  mp.inv_w_end = 1.0 / mp.w[0];
+  mp.gg = c.gas_gamma;
+  mp.lambda_scale = c.lambda_scale;
+  mp.cfl = x->cfg.cfl;
+  mp.hmin = hmin;
+  x->stages = tableau_coefs(c.tableau, x->sc);
+  x->ne = ne;
+  x->N = ne * (size_t)mp.nd;
+  x->nv = c.dim + 2;
+  const size_t len = x->N * (size_t)x->nv;
+  bool ok = hipMalloc(&x->ya, len * sizeof(double)) == hipSuccess &&
+            hipMalloc(&x->yb, len * sizeof(double)) == hipSuccess &&
+            hipMalloc(&x->du, len * sizeof(double)) == hipSuccess &&
+            hipMalloc(&x->deta, ne * sizeof(double)) == hipSuccess &&
+            hipMalloc(&x->gamma_k, ne * sizeof(double)) == hipSuccess &&
+            hipMalloc(&x->iters, ne * sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&x->speed_parts, esrk::kSpeedBlocks * sizeof(double)) == hipSuccess &&
+            hipMalloc(&x->scal, sizeof(DevScalars)) == hipSuccess;
+  x->n_relax_parts = esrk::relax_blocks(mp);
+  ok = ok && hipMalloc(&x->relax_parts, x->n_relax_parts * sizeof(esrk::RelaxPart)) == hipSuccess;
+  if (!ok) {
+    esrk_destroy(x);
+    return ESRK_ENOMEM;
+  }
+  DevScalars init;
+  std::memset(&init, 0, sizeof(init));
+  init.bad_elem = INT64_MAX;
+  init.gamma = 1.0;
+  if (hipMemcpy(x->scal, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) {
+    esrk_destroy(x);
+    return ESRK_EHIP;
+  }
+  *out = x;
+  return ESRK_OK;
+}
+
+void esrk_destroy(esrk_ctx* x) {
+  if (!x) return;
+  (void)hipFree(x->ya);
+  (void)hipFree(x->yb);
+  (void)hipFree(x->du);
+  (void)hipFree(x->deta);
+  (void)hipFree(x->gamma_k);
+  (void)hipFree(x->iters);
+  (void)hipFree(x->speed_parts);
+  (void)hipFree(x->relax_parts);
+  (void)hipFree(x->scal);
+  delete x;
+}
+
+size_t esrk_num_nodes(const esrk_ctx* x) { return x ? x->N : 0; }
+size_t esrk_num_elems(const esrk_ctx* x) { return x ? x->ne : 0; }
+int esrk_num_vars(const esrk_ctx* x) { return x ? x->nv : 0; }
+
+esrk_status esrk_rhs_euler(esrk_ctx* x, const double* u, double* dudt, double* eta_rate,
+                           void* stream) {
+  if (!x || !u || !dudt || (const double*)dudt == u) return ESRK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  x->last = s;
+  esrk::RhsArgs a = base_args(x);
+  a.y = u;
+  a.out = dudt;
+  a.eta = eta_rate;
+  a.stage_mode = 0;
+  return hip_status(esrk::launch_rhs(x->mp, x->cfg.precision, a, s));
+}
+
+esrk_status esrk_rhs_ns(esrk_ctx* x, const double* u, double* dudt, double* eta_rate,
+                        double* visc_diss, void* stream) {
+  if (!x) return ESRK_EINVAL;
+  if (x->cfg.mu > 0.0) return ESRK_ENOTSUP;
+  esrk_status st = esrk_rhs_euler(x, u, dudt, eta_rate, stream);
+  if (st == ESRK_OK && visc_diss)
+    st = hip_status(hipMemsetAsync(visc_diss, 0, x->ne * sizeof(double), (hipStream_t)stream));
+  return st;
+}
+
+esrk_status esrk_rk_stage(esrk_ctx* x, int stage, double dt, const double* u_old,
+                          const double* y_in, double* y_out, double* du, double* deta,
+                          void* stream) {
+  if (!x || stage < 0 || stage >= x->stages || !u_old || !y_in || !du || !deta ||
+      !(dt > 0.0))
+    return ESRK_EINVAL;
+  const bool last = stage == x->stages - 1;
+  if (!last && !y_out) return ESRK_EINVAL;
+  if (y_out && ((const double*)y_out == y_in || (const double*)y_out == u_old))
+    return ESRK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  x->last = s;
+  esrk::RhsArgs a = base_args(x);
+  a.y = y_in;
+  a.u_old = u_old;
+  a.out = last ? nullptr : y_out;
+  a.du = du;
+  a.eta = deta;
+  a.dt_dev = nullptr;
+  a.dt_host = dt;
+  a.sc = x->sc[stage];
+  a.stage_mode = 1;
+  a.first = stage == 0;
+  return hip_status(esrk::launch_rhs(x->mp, x->cfg.precision, a, s));
+}
+
+static esrk::RelaxArgs relax_args(esrk_ctx* x, const double* u_old, const double* du,
+                                  const double* deta, const float* guess, double* gk,
+                                  int32_t* iters) {
+  esrk::RelaxArgs r;
+  r.u_old = u_old;
+  r.du = du;
+  r.deta = deta;
+  r.guess = guess;
+  r.gamma_k = gk;
+  r.iters = iters;
+  r.parts = x->relax_parts;
+  r.scal = x->scal;
+  r.tol = x->cfg.root_tol;
+  r.gamma_max = x->cfg.gamma_max;
+  r.maxit = x->cfg.root_maxit;
+  return r;
+}
+
+esrk_status esrk_local_relaxation_solve(esrk_ctx* x, const double* u_old, const double* du,
+                                        const double* deta, const float* gamma_guess,
+                                        double* gamma_k, double* gamma, int32_t* iters,
+                                        void* stream) {
+  if (!x || !u_old || !du || !deta || !gamma_k || !gamma) return ESRK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  x->last = s;
+  hipError_t e = esrk::launch_relax(
+      x->mp, relax_args(x, u_old, du, deta, gamma_guess, gamma_k, iters), s);
+  if (e == hipSuccess)
+    e = esrk::launch_relax_finish(x->relax_parts, x->n_relax_parts, x->scal, gamma, s);
+  return hip_status(e);
+}
+
+esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamma_k_out,
+                      double* stats_out, void* stream) {
+  if (!x || !u || !t) return ESRK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  x->last = s;
+  const bool cfl = !(dt > 0.0);
+  hipError_t e = hipSuccess;
+  if (cfl) e = esrk::launch_speed(x->mp, u, x->speed_parts, s);
+  const double* yin = u;
+  double* bufs[2] = {x->ya, x->yb};
+  for (int i = 0; i < x->stages && e == hipSuccess; ++i) {
+    const bool last = i == x->stages - 1;
+    esrk::RhsArgs a = base_args(x);
+    a.y = yin;
+    a.u_old = u;
+    a.out = last ? nullptr : bufs[i & 1];
+    a.du = x->du;
+    a.eta = x->deta;
+    if (i == 0) {
+      a.speed_parts = cfl ? x->speed_parts : nullptr;
+      a.dt_host = dt;
+    } else {
+      a.dt_dev = &x->scal->dt;
+    }
+    a.sc = x->sc[i];
+    a.stage_mode = 1;
+    a.first = i == 0;
+    e = esrk::launch_rhs(x->mp, x->cfg.precision, a, s);
+    yin = bufs[i & 1];
+  }
+  double* gk = gamma_k_out ? gamma_k_out : x->gamma_k;
+  if (e == hipSuccess)
+    e = esrk::launch_relax(x->mp, relax_args(x, u, x->du, x->deta, nullptr, gk, x->iters), s);
+  if (e == hipSuccess)
+    e = esrk::launch_apply(x->mp, u, x->du, t, x->relax_parts, x->n_relax_parts, x->scal,
+                           &x->scal->dt, stats_out, s);
+  return hip_status(e);
+}
+
+esrk_status esrk_sync_status(esrk_ctx* x, int64_t* bad_elem) {
+  if (!x) return ESRK_EINVAL;
+  if (hipStreamSynchronize(x->last) != hipSuccess) return ESRK_EHIP;
+  DevScalars h;
+  if (hipMemcpy(&h, x->scal, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return ESRK_EHIP;
+  if (bad_elem) *bad_elem = (h.bad_elem == INT64_MAX) ? -1 : (int64_t)h.bad_elem;
+  const esrk_status st = (esrk_status)h.status;
+  if (h.status != 0) {
+    h.status = 0;
+    h.bad_elem = INT64_MAX;
+    if (hipMemcpy(x->scal, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return ESRK_EHIP;
+  }
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Device-side building blocks of the entropy-stable flux differencing:
+// node primitives, the logarithmic mean and Chandrashekar's entropy-conserving
+// two-point flux (Sec. 3.1 names an entropy-conservative volume flux; this one
+// satisfies Tadmor's condition for S = -rho s/(gamma-1)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace esrk {
+
+// Number of terms kept in the series of the logarithmic mean.  The series
+// branch is taken for f^2 < 1e-2 with f = (a-b)/(a+b); the first dropped term
+// is below 2e-18 (double) or 3e-10 (float) relative.
+template <typename T> struct LnSeries;
+template <> struct LnSeries<double> {
+  static constexpr int terms = 8;
+};
+template <> struct LnSeries<float> {
+  static constexpr int terms = 4;
+};
+
+// F(u) = atanh(f)/f = sum_k u^k / (2k+1),   u = f^2
+template <typename T>
+__device__ __forceinline__ T atanh_over(T u) {
+  constexpr int K = LnSeries<T>::terms;
+  T s = T(1) / T(2 * K - 1);
+#pragma unroll
+  for (int k = K - 2; k >= 0; --k) s = s * u + T(1) / T(2 * k + 1);
+  return s;
+}
+
+// G(u) = f/atanh(f) = 1/F(u), series in u with rational coefficients
+// g_0 = 1, g_k = -sum_{j<k} g_j / (2(k-j)+1).
+template <typename T>
+__device__ __forceinline__ T inv_atanh_over(T u) {
+  constexpr double g[8] = {1.0,
+                           -1.0 / 3.0,
+                           -4.0 / 45.0,
+                           -44.0 / 945.0,
+                           -428.0 / 14175.0,
+                           -10196.0 / 467775.0,
+                           -10719068.0 / 638512875.0,
+                           -25865068.0 / 1915538625.0};
+  constexpr int K = LnSeries<T>::terms;
+  T s = T(g[K - 1]);
+#pragma unroll
+  for (int k = K - 2; k >= 0; --k) s = s * u + T(g[k]);
+  return s;
+}
+
+constexpr double kLnCut = 1e-2;
+
+// Logarithmic mean of a, b given ln a - ln b:
+//   (a - b) / (ln a - ln b) = (a + b) / (2 F(f^2)).
+template <typename T>
+__device__ __forceinline__ T logmean(T a, T b, T dln) {
+  const T s = a + b, d = a - b;
+  const T f = d / s;
+  const T u = f * f;
+  if (u < T(kLnCut)) return T(0.5) * s * inv_atanh_over(u);
+  return d / dln;
+}
+
+// 1 / logmean(a, b) given ln a - ln b.
+template <typename T>
+__device__ __forceinline__ T inv_logmean(T a, T b, T dln) {
+  const T s = a + b, d = a - b;
+  const T rs = T(1) / s;
+  const T f = d * rs;
+  const T u = f * f;
+  if (u < T(kLnCut)) return T(2) * rs * atanh_over(u);
+  return dln / d;
+}
+
+// Logarithmic mean without precomputed logarithms (interface pairs).
+template <typename T>
+__device__ __forceinline__ T logmean_direct(T a, T b) {
+  const T s = a + b, d = a - b;
+  const T f = d / s;
+  const T u = f * f;
+  if (u < T(kLnCut)) return T(0.5) * s * inv_atanh_over(u);
+  return d / log(a / b);
+}
+template <typename T>
+__device__ __forceinline__ T inv_logmean_direct(T a, T b) {
+  const T s = a + b, d = a - b;
+  const T rs = T(1) / s;
+  const T f = d * rs;
+  const T u = f * f;
+  if (u < T(kLnCut)) return T(2) * rs * atanh_over(u);
+  return log(a / b) / d;
+}
+
+// Primitive set of one node used by the two-point flux.
+template <typename T, int DIM>
+struct Prim {
+  T rho, beta, v[DIM], v2;  // beta = rho / (2 p), v2 = |v|^2
+};
+
+template <typename T, int DIM>
+__device__ __forceinline__ void prim_from_cons(const T* q, T gg, Prim<T, DIM>& P, T& p) {
+  P.rho = q[0];
+  const T inv = T(1) / q[0];
+  P.v2 = T(0);
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    P.v[k] = q[1 + k] * inv;
+    P.v2 += P.v[k] * P.v[k];
+  }
+  p = (gg - T(1)) * (q[DIM + 1] - T(0.5) * P.rho * P.v2);
+  P.beta = T(0.5) * P.rho / p;
+}
+
+// Chandrashekar's flux in direction m given rho^ln, 1/beta^ln:
+//   f_rho = rho^ln {v_m};  f_mk = f_rho {v_k} + delta_km {rho} / (2 {beta});
+//   f_E = f_rho (1/(2 (gamma-1) beta^ln) - {|v|^2}/2) + sum_k {v_k} f_mk.
+template <typename T, int DIM>
+__device__ __forceinline__ void ec_flux_from_means(int m, const Prim<T, DIM>& A,
+                                                   const Prim<T, DIM>& B, T rho_ln,
+                                                   T inv_beta_ln, T half_inv_gm1,
+                                                   T* F) {
+  T va[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) va[k] = T(0.5) * (A.v[k] + B.v[k]);
+  T vn = va[0];
+#pragma unroll
+  for (int k = 1; k < DIM; ++k) vn = (m == k) ? va[k] : vn;
+  const T p_hat = (A.rho + B.rho) / (T(2) * (A.beta + B.beta));
+  const T frho = rho_ln * vn;
+  F[0] = frho;
+  T fe = frho * (half_inv_gm1 * inv_beta_ln - T(0.25) * (A.v2 + B.v2));
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const T fm = frho * va[k] + ((m == k) ? p_hat : T(0));
+    F[1 + k] = fm;
+    fe += va[k] * fm;
+  }
+  F[DIM + 1] = fe;
+}
+
+}  // namespace esrk

@@ -1,0 +1,101 @@
+// Internal declarations shared by the HIP sources of libesrk (not part of the
+// C-ABI).  Nothing here is shared with the CPU oracle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/esrk.h"
+
+namespace esrk {
+
+constexpr int kMaxN = 6;  // degree <= 5
+
+// Device-resident scalars of one context.
+struct DevScalars {
+  double dt;           // step size of the current step
+  double gamma;        // global relaxation parameter of the last solve
+  int status;          // latched esrk_status (0 = ok)
+  int pad0;
+  long long bad_elem;  // smallest offending element, or INT64_MAX
+};
+
+// Per-block partial results (no same-address atomics on the hot path; the
+// consumer kernel reduces the partials in a fixed order).
+constexpr int kSpeedBlocks = 256;  // blocks of the wave-speed pass
+struct RelaxPart {
+  double gmin;      // min over the block's elements of gamma_k (+INF if none)
+  int n_inactive;   // elements with gamma_k = +INF
+  int max_iters;    // largest number of phi evaluations
+};
+
+// Mesh + operator tables passed by value to kernels.
+struct MeshParams {
+  int dim, n, nd, ne;
+  int nel[3];
+  double two_over_h[3];  // metric of the affine element map, 2/h_m
+  double half_h[3];      // h_m / 2
+  double D2[kMaxN * kMaxN];  // 2 D_ab, D = Lobatto differentiation matrix
+  double w[kMaxN];           // Lobatto weights
+  double inv_w_end;          // 1 / w_0 = 1 / w_p
+  double gg;                 // ratio of specific heats
+  double lambda_scale;
+  double cfl, hmin;
+};
+
+// Runge-Kutta stage coefficients in the two-register form used on the device:
+//   y_{i+1} = alpha_i u_old + beta_i y_i + c_i dt k_i,   du += b_i dt k_i.
+struct StageCoef {
+  double alpha, beta, c, b;
+};
+
+struct RhsArgs {
+  const double* y;      // state the right-hand side is evaluated at
+  const double* u_old;  // stage mode: step start state
+  double* out;          // plain mode: dudt; stage mode: y_{i+1} (nullable on last stage)
+  double* du;           // stage mode: increment accumulator
+  double* eta;          // plain: eta_rate (nullable); stage: deta accumulator
+  const double* dt_dev; // stage mode: device dt (nullable -> dt_host or speed_parts)
+  const double* speed_parts;  // stage 0 with CFL step: kSpeedBlocks wave-speed maxima
+  double dt_host;
+  StageCoef sc;
+  int stage_mode;       // 0: plain right-hand side, 1: RK stage
+  int first;            // stage 0 overwrites du/deta
+  DevScalars* scal;
+};
+
+// Host tables (Lobatto nodes/weights/derivative matrix), built in extended
+// precision from the closed forms.
+void lobatto_tables(int deg, double* x, double* w, double* D);
+
+// Launchers (return hipError_t).
+hipError_t launch_rhs(const MeshParams& mp, int precision, const RhsArgs& a,
+                      hipStream_t s);
+
+struct RelaxArgs {
+  const double* u_old;
+  const double* du;
+  const double* deta;
+  const float* guess;  // nullable
+  double* gamma_k;
+  int32_t* iters;      // nullable
+  RelaxPart* parts;    // one per block
+  DevScalars* scal;
+  double tol, gamma_max;
+  int maxit;
+};
+int relax_blocks(const MeshParams& mp);
+hipError_t launch_relax(const MeshParams& mp, const RelaxArgs& a, hipStream_t s);
+// gamma = min over partials (1 if all inactive) -> *gamma and scal->gamma
+hipError_t launch_relax_finish(const RelaxPart* parts, int nparts, DevScalars* scal,
+                               double* gamma, hipStream_t s);
+// wave-speed maxima per block of the state u -> parts[kSpeedBlocks]
+hipError_t launch_speed(const MeshParams& mp, const double* u, double* parts, hipStream_t s);
+// u <- u + gamma du with gamma reduced from the relaxation partials (skipped
+// when an error is latched); t <- t + gamma dt; optional stats.
+hipError_t launch_apply(const MeshParams& mp, double* u, const double* du, double* t,
+                        const RelaxPart* parts, int nparts, DevScalars* scal,
+                        const double* dt_dev, double* stats_out, hipStream_t s);
+
+}  // namespace esrk

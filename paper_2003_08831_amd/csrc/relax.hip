@@ -1,0 +1,500 @@
+// Local relaxation kernels (Sec. 2: local relaxation equation; the theorem
+// that gamma = min_k gamma_k keeps every element's entropy inequality) and
+// the step bookkeeping kernels (CFL step size, global minimum, relaxed update).
+//
+// Per element k, with du = u_new - u_old and deta_k = eta_k^new - eta_k^old,
+//   r_k(g) = eta_k(u_old + g du) - eta_k(u_old) - g deta_k = g a_k + B_k(g),
+//   a_k    = sum_i M_i w(u_old,i).du_i - deta_k          (= phi_k(0)),
+//   B_k(g) = sum_i M_i [S(u_i + g du_i) - S(u_i) - g w(u_i).du_i]   (>= 0),
+// and phi_k(g) = r_k(g)/g = a_k + B_k(g)/g.  B_k is the relative entropy of the
+// relaxed state with respect to u_old; per node it is evaluated without
+// cancellation from the ratios y = rho'/rho and x = p'/p:
+//   S(u') - S(u) - w(u).(u'-u) = rho'/(g-1) h(x/y) + rho k(y) + rho rho'/(2p) |v'-v|^2,
+//   h(z) = z - 1 - ln z,   k(y) = y ln y - y + 1,
+// both taken from their Taylor series near 1.  So phi_k is accurate to round-off
+// in a_k even when the entropy change of an element is tiny.
+//
+// Mapping: one segment of G lanes (G = next power of two >= nodes per element,
+// at most 64) per element; each lane keeps its nodes' u_old and du in registers
+// for the whole solve, the element sums are segment shuffles.  The root is
+// bracketed from [0, 1] and refined by Illinois-modified regula falsi, each new
+// point kept at least tol/4 inside the bracket, until the bracket is narrower
+// than tol * max(1, gamma); the lower end (phi <= 0) is returned.
+#include <cfloat>
+
+#include "internal.h"
+
+namespace esrk {
+
+__device__ __forceinline__ void latch_r(DevScalars* s, int code, long long elem) {
+  atomicCAS(&s->status, 0, code);
+  atomicMin((unsigned long long*)&s->bad_elem, (unsigned long long)elem);
+}
+
+__device__ __forceinline__ double dbits(unsigned long long b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ unsigned long long bitsd(double d) {
+  return (unsigned long long)__double_as_longlong(d);
+}
+
+// h(1+t) = t - log1p(t) = sum_{n>=2} (-1)^n t^n / n
+__device__ __forceinline__ double h_rel(double t) {
+  if (fabs(t) < 1e-2) {
+    double s = -1.0 / 9.0;
+    s = s * t + 1.0 / 8.0;
+    s = s * t - 1.0 / 7.0;
+    s = s * t + 1.0 / 6.0;
+    s = s * t - 1.0 / 5.0;
+    s = s * t + 1.0 / 4.0;
+    s = s * t - 1.0 / 3.0;
+    s = s * t + 1.0 / 2.0;
+    return s * t * t;
+  }
+  return t - log1p(t);
+}
+// k(1+t) = (1+t) log1p(t) - t = sum_{n>=2} (-1)^n t^n / (n (n-1))
+__device__ __forceinline__ double k_rel(double t) {
+  if (fabs(t) < 1e-2) {
+    double s = -1.0 / 72.0;
+    s = s * t + 1.0 / 56.0;
+    s = s * t - 1.0 / 42.0;
+    s = s * t + 1.0 / 30.0;
+    s = s * t - 1.0 / 20.0;
+    s = s * t + 1.0 / 12.0;
+    s = s * t - 1.0 / 6.0;
+    s = s * t + 1.0 / 2.0;
+    return s * t * t;
+  }
+  return (1.0 + t) * log1p(t) - t;
+}
+
+template <int G>
+__device__ __forceinline__ double seg_sum(double x) {
+#pragma unroll
+  for (int off = G / 2; off >= 1; off /= 2) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+template <int DIM, int N>
+struct RelaxCfg {
+  static constexpr int ND = (DIM == 1) ? N : (DIM == 2) ? N * N : N * N * N;
+  static constexpr int NV = DIM + 2;
+  static constexpr int G = ND <= 2 ? 2 : ND <= 4 ? 4 : ND <= 8 ? 8 : ND <= 16 ? 16
+                           : ND <= 32 ? 32 : 64;
+  static constexpr int NPL = (ND + G - 1) / G;
+  static constexpr int SEGS = 64 / G;
+  static constexpr int THREADS = 256;
+  static constexpr int EPB = (THREADS / 64) * SEGS;  // elements per block
+};
+
+template <int DIM, int N>
+__global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const RelaxArgs a) {
+  using C = RelaxCfg<DIM, N>;
+  constexpr int NV = C::NV, G = C::G, NPL = C::NPL, ND = C::ND;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int seg = lane / G;
+  const int sl = lane - seg * G;
+  const int k = blockIdx.x * C::EPB + wave * C::SEGS + seg;
+  const bool valid = k < mp.ne;
+  const long long Ntot = (long long)mp.ne * ND;
+  const double gg = mp.gg, gm1 = gg - 1.0;
+
+  // per-node constants along the relaxation line
+  double rho[NPL], mom[NPL][DIM], ene[NPL], dr[NPL], dm[NPL][DIM], dE[NPL];
+  double invrho[NPL], invp[NPL], m2[NPL], beta[NPL], Mi[NPL];
+  bool has[NPL];
+  double A = 0.0, scale = 0.0;
+#pragma unroll
+  for (int j = 0; j < NPL; ++j) {
+    const int i = sl + j * G;
+    has[j] = valid && i < ND;
+    const long long gi = (long long)k * ND + i;
+    if (has[j]) {
+      rho[j] = a.u_old[gi];
+      dr[j] = a.du[gi];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        mom[j][d] = a.u_old[(1 + d) * Ntot + gi];
+        dm[j][d] = a.du[(1 + d) * Ntot + gi];
+      }
+      ene[j] = a.u_old[(NV - 1) * Ntot + gi];
+      dE[j] = a.du[(NV - 1) * Ntot + gi];
+    } else {
+      rho[j] = 1.0;
+      dr[j] = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) mom[j][d] = dm[j][d] = 0.0;
+      ene[j] = 1.0;
+      dE[j] = 0.0;
+    }
+    invrho[j] = 1.0 / rho[j];
+    double mm = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) mm += mom[j][d] * mom[j][d];
+    m2[j] = mm;
+    const double p = gm1 * (ene[j] - 0.5 * mm * invrho[j]);
+    invp[j] = 1.0 / p;
+    beta[j] = 0.5 * rho[j] * invp[j];
+    double M = 1.0;
+    {
+      int ii = i;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int im = ii % N;
+        ii /= N;
+        M *= mp.half_h[d] * mp.w[im];
+      }
+    }
+    Mi[j] = has[j] ? M : 0.0;
+    // w(u_old).du and its round-off scale
+    const double s_phys = log(p) - gg * log(rho[j]);
+    const double v2 = mm * invrho[j] * invrho[j];
+    double t = ((gg - s_phys) / gm1 - beta[j] * v2) * dr[j];
+    double sc = fabs(t);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double td = 2.0 * beta[j] * mom[j][d] * invrho[j] * dm[j][d];
+      t += td;
+      sc += fabs(td);
+    }
+    const double te = -2.0 * beta[j] * dE[j];
+    t += te;
+    sc += fabs(te);
+    A += Mi[j] * t;
+    scale += Mi[j] * sc;
+  }
+  A = seg_sum<G>(A);
+  scale = seg_sum<G>(scale);
+  const double deta = valid ? a.deta[k] : 0.0;
+  const double phi0 = A - deta;
+  const double noise = 64.0 * DBL_EPSILON * (scale + fabs(deta));
+
+  // relative entropy sum B(g) and admissibility along the line
+  auto Bsum = [&](double g, bool& ok) -> double {
+    double part = 0.0;
+    double bad = 0.0;
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) {
+      const double r0 = rho[j];
+      const double drg = g * dr[j];
+      const double r1 = r0 + drg;
+      double mdm = 0.0, dm2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double dmg = g * dm[j][d];
+        mdm += mom[j][d] * dmg;
+        dm2 += dmg * dmg;
+      }
+      const double q = 1.0 / (r0 * r1);
+      const double dke = (r0 * (2.0 * mdm + dm2) - drg * m2[j]) * q;
+      const double dp = gm1 * (g * dE[j] - 0.5 * dke);
+      const double tr = drg * invrho[j];
+      const double tp = dp * invp[j];
+      const bool okn = (r1 > 0.0) && (1.0 + tp > 0.0);
+      if (!okn && has[j]) bad += 1.0;
+      double Dn = 0.0;
+      if (okn) {
+        const double tz = (tp - tr) * r0 * r0 * q;
+        double dv2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const double dv = (g * dm[j][d] - drg * mom[j][d] * invrho[j]) * r0 * q;
+          dv2 += dv * dv;
+        }
+        Dn = r1 * h_rel(tz) / gm1 + r0 * k_rel(tr) + beta[j] * r1 * dv2;
+      }
+      part += Mi[j] * Dn;
+    }
+    part = seg_sum<G>(part);
+    bad = seg_sum<G>(bad);
+    ok = bad == 0.0;
+    return part;
+  };
+
+  // root solve: all lanes iterate together; a segment stops updating once done
+  const double tol = a.tol, gmax = a.gamma_max;
+  double lo = 0.0, flo = phi0, hi = 1.0, fhi = 0.0, gk = 1.0, g_trial = 1.0;
+  bool hi_known = false, done = !valid;
+  int side = 0, its = 0;
+  const bool have_guess = a.guess != nullptr;
+  while (__any(!done)) {
+    bool ok = true;
+    const double B = Bsum(done ? 1.0 : g_trial, ok);
+    if (done) continue;
+    ++its;
+    const double f = ok ? phi0 + B / g_trial : INFINITY;
+    if (its == 1) {
+      const double q = ok ? B : INFINITY;  // r(1) - phi(0)
+      if (q <= noise) {
+        gk = INFINITY;
+        done = true;
+        continue;
+      }
+      if (!(phi0 < 0.0)) {
+        gk = 0.0;
+        done = true;
+        if (sl == 0) latch_r(a.scal, ESRK_ENOROOT, k);
+        continue;
+      }
+    }
+    if (f <= 0.0) {
+      if (hi_known && side == -1) fhi *= 0.5;
+      lo = g_trial;
+      flo = f;
+      side = -1;
+    } else {
+      if (hi_known && side == +1) flo *= 0.5;
+      hi = g_trial;
+      fhi = f;
+      hi_known = true;
+      side = +1;
+    }
+    if (!hi_known) {
+      if (lo >= gmax) {
+        gk = gmax;
+        done = true;
+      } else {
+        g_trial = fmin(2.0 * lo, gmax);
+      }
+      continue;
+    }
+    const double tw = tol * fmax(1.0, hi);
+    if (hi - lo <= tw || its >= a.maxit) {
+      gk = lo;
+      done = true;
+      continue;
+    }
+    double g;
+    if (its == 1 && have_guess) {
+      g = (double)a.guess[k];
+    } else if (isinf(fhi)) {
+      g = 0.5 * (lo + hi);
+    } else {
+      g = lo - flo * (hi - lo) / (fhi - flo);
+    }
+    if (!(g == g)) g = 0.5 * (lo + hi);
+    g = fmin(fmax(g, lo + 0.25 * tw), hi - 0.25 * tw);
+    g_trial = g;
+  }
+
+  // per-element outputs and the block partials (min gamma, inactive count, iterations)
+  const bool leader = valid && sl == 0;
+  if (leader) {
+    a.gamma_k[k] = gk;
+    if (a.iters) a.iters[k] = its;
+  }
+  double gl = (leader && !isinf(gk) && gk > 0.0) ? gk : INFINITY;
+  int inact = (leader && isinf(gk)) ? 1 : 0;
+  int itl = leader ? its : 0;
+#pragma unroll
+  for (int off = 32; off >= 1; off /= 2) {
+    gl = fmin(gl, __shfl_xor(gl, off, 64));
+    inact += __shfl_xor(inact, off, 64);
+    itl = max(itl, __shfl_xor(itl, off, 64));
+  }
+  __shared__ double wg[C::THREADS / 64];
+  __shared__ int wi[C::THREADS / 64], wm[C::THREADS / 64];
+  if (lane == 0) {
+    wg[wave] = gl;
+    wi[wave] = inact;
+    wm[wave] = itl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    RelaxPart p{INFINITY, 0, 0};
+    for (int q = 0; q < C::THREADS / 64; ++q) {
+      p.gmin = fmin(p.gmin, wg[q]);
+      p.n_inactive += wi[q];
+      p.max_iters = max(p.max_iters, wm[q]);
+    }
+    a.parts[blockIdx.x] = p;
+  }
+}
+
+template <int DIM, int N>
+static int relax_epb() {
+  return RelaxCfg<DIM, N>::EPB;
+}
+
+int relax_blocks(const MeshParams& mp) {
+  int epb = 1;
+#define ESRK_EPB(D)                          \
+  switch (mp.n) {                            \
+    case 2: epb = relax_epb<D, 2>(); break;  \
+    case 3: epb = relax_epb<D, 3>(); break;  \
+    case 4: epb = relax_epb<D, 4>(); break;  \
+    case 5: epb = relax_epb<D, 5>(); break;  \
+    case 6: epb = relax_epb<D, 6>(); break;  \
+  }
+  if (mp.dim == 1) { ESRK_EPB(1) }
+  if (mp.dim == 2) { ESRK_EPB(2) }
+  if (mp.dim == 3) { ESRK_EPB(3) }
+#undef ESRK_EPB
+  return (mp.ne + epb - 1) / epb;
+}
+
+template <int DIM, int N>
+static hipError_t relax_one(const MeshParams& mp, const RelaxArgs& a, hipStream_t s) {
+  using C = RelaxCfg<DIM, N>;
+  const int blocks = (mp.ne + C::EPB - 1) / C::EPB;
+  hipLaunchKernelGGL((relax_kernel<DIM, N>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
+  return hipGetLastError();
+}
+
+template <int DIM>
+static hipError_t relax_dim(const MeshParams& mp, const RelaxArgs& a, hipStream_t s) {
+  switch (mp.n) {
+    case 2: return relax_one<DIM, 2>(mp, a, s);
+    case 3: return relax_one<DIM, 3>(mp, a, s);
+    case 4: return relax_one<DIM, 4>(mp, a, s);
+    case 5: return relax_one<DIM, 5>(mp, a, s);
+    case 6: return relax_one<DIM, 6>(mp, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_relax(const MeshParams& mp, const RelaxArgs& a, hipStream_t s) {
+  if (mp.dim == 1) return relax_dim<1>(mp, a, s);
+  if (mp.dim == 2) return relax_dim<2>(mp, a, s);
+  if (mp.dim == 3) return relax_dim<3>(mp, a, s);
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- bookkeeping
+
+// Block-wide reduction helpers over 256 threads (4 waves).
+__device__ __forceinline__ double block_min256(double x, double* sh) {
+#pragma unroll
+  for (int off = 32; off >= 1; off /= 2) x = fmin(x, __shfl_xor(x, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+  __syncthreads();
+  x = fmin(fmin(sh[0], sh[1]), fmin(sh[2], sh[3]));
+  __syncthreads();
+  return x;
+}
+
+__device__ __forceinline__ double block_sum256(double x, double* sh) {
+#pragma unroll
+  for (int off = 32; off >= 1; off /= 2) x += __shfl_xor(x, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+  __syncthreads();
+  x = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return x;
+}
+
+// Maximum over the block's nodes of sum_m (|v_m| + c).
+template <int DIM>
+__global__ void __launch_bounds__(256) speed_kernel(const double* u, long long Ntot, double gg,
+                                                    double* parts) {
+  double best = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < Ntot;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double rho = u[i];
+    double mm = 0.0, v[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double m = u[(1 + d) * Ntot + i];
+      v[d] = m / rho;
+      mm += v[d] * m;
+    }
+    const double p = (gg - 1.0) * (u[(DIM + 1) * Ntot + i] - 0.5 * mm);
+    const double c = sqrt(gg * p / rho);
+    double sp = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) sp += fabs(v[d]) + c;
+    best = fmax(best, sp);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off /= 2) best = fmax(best, __shfl_xor(best, off, 64));
+  __shared__ double sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) parts[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+hipError_t launch_speed(const MeshParams& mp, const double* u, double* parts, hipStream_t s) {
+  const long long Ntot = (long long)mp.ne * mp.nd;
+  if (mp.dim == 1)
+    hipLaunchKernelGGL(speed_kernel<1>, dim3(kSpeedBlocks), dim3(256), 0, s, u, Ntot, mp.gg, parts);
+  else if (mp.dim == 2)
+    hipLaunchKernelGGL(speed_kernel<2>, dim3(kSpeedBlocks), dim3(256), 0, s, u, Ntot, mp.gg, parts);
+  else
+    hipLaunchKernelGGL(speed_kernel<3>, dim3(kSpeedBlocks), dim3(256), 0, s, u, Ntot, mp.gg, parts);
+  return hipGetLastError();
+}
+
+// gamma = min over the relaxation partials (fixed order per block).
+__device__ __forceinline__ double reduce_gamma(const RelaxPart* parts, int nparts, double* sh) {
+  double g = INFINITY;
+  for (int q = threadIdx.x; q < nparts; q += blockDim.x) g = fmin(g, parts[q].gmin);
+  g = block_min256(g, sh);
+  return isinf(g) ? 1.0 : g;
+}
+
+__global__ void __launch_bounds__(256) relax_finish_kernel(const RelaxPart* parts, int nparts,
+                                                           DevScalars* s, double* gamma) {
+  __shared__ double sh[4];
+  const double g = reduce_gamma(parts, nparts, sh);
+  if (threadIdx.x == 0) {
+    s->gamma = g;
+    if (gamma) *gamma = g;
+  }
+}
+
+hipError_t launch_relax_finish(const RelaxPart* parts, int nparts, DevScalars* scal,
+                               double* gamma, hipStream_t s) {
+  hipLaunchKernelGGL(relax_finish_kernel, dim3(1), dim3(256), 0, s, parts, nparts, scal, gamma);
+  return hipGetLastError();
+}
+
+// u <- u + gamma du (skipped when a device error is latched), t <- t + gamma dt.
+// Every block reduces the relaxation partials itself (same order, same gamma).
+__global__ void __launch_bounds__(256) apply_kernel(double* u, const double* du, long long len,
+                                                    double* t, const RelaxPart* parts,
+                                                    int nparts, DevScalars* s,
+                                                    const double* dt_dev, double* stats_out) {
+  __shared__ double sh[4];
+  const double g = reduce_gamma(parts, nparts, sh);
+  const bool err = s->status != 0;
+  if (!err) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len;
+         i += (long long)gridDim.x * blockDim.x)
+      u[i] = u[i] + g * du[i];
+  }
+  if (blockIdx.x == 0) {
+    double inact = 0.0;
+    if (stats_out) {
+      for (int q = threadIdx.x; q < nparts; q += blockDim.x) inact += parts[q].n_inactive;
+      inact = block_sum256(inact, sh);
+    }
+    if (threadIdx.x == 0) {
+      const double dt = *dt_dev;
+      double tn = *t;
+      if (!err) {
+        tn = tn + g * dt;
+        *t = tn;
+      }
+      s->gamma = g;
+      if (stats_out) {
+        stats_out[0] = g;
+        stats_out[1] = dt;
+        stats_out[2] = tn;
+        stats_out[3] = inact;
+      }
+    }
+  }
+}
+
+hipError_t launch_apply(const MeshParams& mp, double* u, const double* du, double* t,
+                        const RelaxPart* parts, int nparts, DevScalars* scal,
+                        const double* dt_dev, double* stats_out, hipStream_t s) {
+  const long long len = (long long)(mp.dim + 2) * mp.ne * mp.nd;
+  long long blocks = (len + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(apply_kernel, dim3(blocks), dim3(256), 0, s, u, du, len, t, parts, nparts,
+                     scal, dt_dev, stats_out);
+  return hipGetLastError();
+}
+
+}  // namespace esrk

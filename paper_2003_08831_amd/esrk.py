@@ -1,0 +1,175 @@
+"""Thin ctypes binding of libesrk.so (C-ABI in include/esrk.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device arrays are torch tensors on the HIP device (float64, C
+contiguous) or raw device addresses (int).  Loading fails loudly if the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libesrk.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "esrk.h")
+
+FP64, FP32_FLUX = 0, 1
+SSPRK33, RK44 = 0, 1
+
+STATUS = {0: "OK", 1: "EINVAL", 2: "EHIP", 3: "ENOMEM", 4: "ENOROOT", 5: "ENONPHYS",
+          6: "ENAN", 7: "ENOTSUP"}
+
+
+class EsrkError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        super().__init__(f"{where}: {STATUS.get(code, code)}")
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("deg", C.c_int), ("nel", C.c_int * 3),
+        ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+        ("gas_gamma", C.c_double), ("gas_r", C.c_double), ("mu", C.c_double),
+        ("prandtl", C.c_double), ("lambda_scale", C.c_double),
+        ("precision", C.c_int), ("tableau", C.c_int), ("cfl", C.c_double),
+        ("root_tol", C.c_double), ("root_maxit", C.c_int), ("gamma_max", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def declared_symbols():
+    """Function names declared in include/esrk.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(esrk_[a-z_]+)\s*\(", text)))
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library missing: {LIB_PATH} (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, st = C.c_void_p, C.c_double, C.c_int
+    L.esrk_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+    L.esrk_create.restype = st
+    L.esrk_destroy.argtypes = [vp]
+    L.esrk_destroy.restype = None
+    L.esrk_num_nodes.argtypes = [vp]
+    L.esrk_num_nodes.restype = C.c_size_t
+    L.esrk_num_elems.argtypes = [vp]
+    L.esrk_num_elems.restype = C.c_size_t
+    L.esrk_num_vars.argtypes = [vp]
+    L.esrk_num_vars.restype = C.c_int
+    L.esrk_rhs_euler.argtypes = [vp, vp, vp, vp, vp]
+    L.esrk_rhs_euler.restype = st
+    L.esrk_rhs_ns.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.esrk_rhs_ns.restype = st
+    L.esrk_rk_stage.argtypes = [vp, C.c_int, dp, vp, vp, vp, vp, vp, vp]
+    L.esrk_rk_stage.restype = st
+    L.esrk_local_relaxation_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.esrk_local_relaxation_solve.restype = st
+    L.esrk_step.argtypes = [vp, vp, vp, dp, vp, vp, vp]
+    L.esrk_step.restype = st
+    L.esrk_sync_status.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.esrk_sync_status.restype = st
+    L.esrk_status_str.argtypes = [st]
+    L.esrk_status_str.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise EsrkError(rc, where)
+
+
+def make_config(dim, deg, nel, lo, hi, gas_gamma=1.4, gas_r=1.0, mu=0.0, prandtl=0.72,
+                lambda_scale=1.0, precision=FP64, tableau=SSPRK33, cfl=0.5,
+                root_tol=1e-12, root_maxit=60, gamma_max=4.0) -> Config:
+    c = Config()
+    c.dim, c.deg = dim, deg
+    nel = list(nel) + [1] * (3 - len(nel))
+    lo = list(lo) + [0.0] * (3 - len(lo))
+    hi = list(hi) + [1.0] * (3 - len(hi))
+    for q in range(3):
+        c.nel[q], c.lo[q], c.hi[q] = int(nel[q]), float(lo[q]), float(hi[q])
+    c.gas_gamma, c.gas_r, c.mu, c.prandtl = gas_gamma, gas_r, mu, prandtl
+    c.lambda_scale, c.precision, c.tableau, c.cfl = lambda_scale, precision, tableau, cfl
+    c.root_tol, c.root_maxit, c.gamma_max = root_tol, root_maxit, gamma_max
+    return c
+
+
+class Context:
+    """Owns one esrk_ctx.  Methods mirror the C entry points one to one."""
+
+    def __init__(self, cfg: Config):
+        L = load()
+        h = C.c_void_p()
+        _check(L.esrk_create(C.byref(cfg), C.byref(h)), "esrk_create")
+        self._h = h
+        self.cfg = cfg
+        self.N = int(L.esrk_num_nodes(h))
+        self.ne = int(L.esrk_num_elems(h))
+        self.nv = int(L.esrk_num_vars(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().esrk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rhs_euler(self, u, dudt, eta_rate=None, stream=None):
+        _check(load().esrk_rhs_euler(self._h, _ptr(u), _ptr(dudt), _ptr(eta_rate),
+                                     _stream(stream)), "esrk_rhs_euler")
+
+    def rhs_ns(self, u, dudt, eta_rate=None, visc_diss=None, stream=None):
+        _check(load().esrk_rhs_ns(self._h, _ptr(u), _ptr(dudt), _ptr(eta_rate),
+                                  _ptr(visc_diss), _stream(stream)), "esrk_rhs_ns")
+
+    def rk_stage(self, stage, dt, u_old, y_in, y_out, du, deta, stream=None):
+        _check(load().esrk_rk_stage(self._h, int(stage), float(dt), _ptr(u_old), _ptr(y_in),
+                                    _ptr(y_out), _ptr(du), _ptr(deta), _stream(stream)),
+               "esrk_rk_stage")
+
+    def local_relaxation_solve(self, u_old, du, deta, gamma_k, gamma, gamma_guess=None,
+                               iters=None, stream=None):
+        _check(load().esrk_local_relaxation_solve(
+            self._h, _ptr(u_old), _ptr(du), _ptr(deta), _ptr(gamma_guess), _ptr(gamma_k),
+            _ptr(gamma), _ptr(iters), _stream(stream)), "esrk_local_relaxation_solve")
+
+    def step(self, u, t, dt=0.0, gamma_k=None, stats=None, stream=None):
+        _check(load().esrk_step(self._h, _ptr(u), _ptr(t), float(dt), _ptr(gamma_k),
+                                _ptr(stats), _stream(stream)), "esrk_step")
+
+    def sync_status(self):
+        bad = C.c_int64(-1)
+        rc = load().esrk_sync_status(self._h, C.byref(bad))
+        return rc, bad.value
