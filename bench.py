@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=3)
     p.add_argument("--kernel-reps", type=int, default=50)
+    p.add_argument("--copy-calib", action="store_true",
+                   help="run one 256 MiB device-to-device copy first (counter calibration)")
     return p.parse_args()
 
 
@@ -128,6 +130,13 @@ def main():
         sys.exit(1)
     from paper_2003_08831_amd import esrk
     from paper_2003_08831_amd import inputs as I
+
+    if a.copy_calib:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ctx64, u64, r64 = run_mode(esrk, I, torch, esrk.FP64, a.steps, a.warmup)
     ctx32, u32, r32 = run_mode(esrk, I, torch, esrk.FP32_FLUX, a.steps, a.warmup)

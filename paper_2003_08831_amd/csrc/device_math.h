@@ -50,45 +50,45 @@ __device__ __forceinline__ T inv_atanh_over(T u) {
 
 constexpr double kLnCut = 1e-2;
 
-// Logarithmic mean of a, b given ln a - ln b:
-//   (a - b) / (ln a - ln b) = (a + b) / (2 F(f^2)).
-template <typename T>
-__device__ __forceinline__ T logmean(T a, T b, T dln) {
-  const T s = a + b, d = a - b;
-  const T f = d / s;
-  const T u = f * f;
-  if (u < T(kLnCut)) return T(0.5) * s * inv_atanh_over(u);
-  return d / dln;
+// Reciprocal: hardware estimate refined by Newton steps (two in double, which
+// reach full precision from any estimate better than 2^-14; one in float).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+__device__ __forceinline__ float rcp(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(fmaf(-x, r, 1.0f), r, r);
 }
 
-// 1 / logmean(a, b) given ln a - ln b.
+// The three averages of the entropy-conservative flux for one node pair:
+// rho^ln, 1/beta^ln and p_hat = {rho}/(2 {beta}).  The logarithmic mean
+// (a-b)/(ln a - ln b) = (a+b)/(2 F(f^2)), f = (a-b)/(a+b), is taken from the
+// series (no logarithm) unless a jump is large; two reciprocals in the common
+// case.
 template <typename T>
-__device__ __forceinline__ T inv_logmean(T a, T b, T dln) {
-  const T s = a + b, d = a - b;
-  const T rs = T(1) / s;
-  const T f = d * rs;
-  const T u = f * f;
-  if (u < T(kLnCut)) return T(2) * rs * atanh_over(u);
-  return dln / d;
-}
-
-// Logarithmic mean without precomputed logarithms (interface pairs).
+struct PairMeans {
+  T rho_ln, inv_beta_ln, p_hat;
+};
 template <typename T>
-__device__ __forceinline__ T logmean_direct(T a, T b) {
-  const T s = a + b, d = a - b;
-  const T f = d / s;
-  const T u = f * f;
-  if (u < T(kLnCut)) return T(0.5) * s * inv_atanh_over(u);
-  return d / log(a / b);
-}
-template <typename T>
-__device__ __forceinline__ T inv_logmean_direct(T a, T b) {
-  const T s = a + b, d = a - b;
-  const T rs = T(1) / s;
-  const T f = d * rs;
-  const T u = f * f;
-  if (u < T(kLnCut)) return T(2) * rs * atanh_over(u);
-  return log(a / b) / d;
+__device__ __forceinline__ PairMeans<T> pair_means(T ra, T rb, T ba, T bb) {
+  const T sr = ra + rb, dr = ra - rb;
+  const T sb = ba + bb, db = ba - bb;
+  const T rsr = rcp(sr), rsb = rcp(sb);
+  const T fr = dr * rsr, fb = db * rsb;
+  const T ur = fr * fr, ub = fb * fb;
+  PairMeans<T> m;
+  m.p_hat = T(0.5) * sr * rsb;
+  if (ur < T(kLnCut) && ub < T(kLnCut)) {
+    m.rho_ln = T(0.5) * sr * inv_atanh_over(ur);
+    m.inv_beta_ln = T(2) * rsb * atanh_over(ub);
+  } else {
+    m.rho_ln = (ur < T(kLnCut)) ? T(0.5) * sr * inv_atanh_over(ur) : dr / log(ra / rb);
+    m.inv_beta_ln = (ub < T(kLnCut)) ? T(2) * rsb * atanh_over(ub) : log(ba / bb) / db;
+  }
+  return m;
 }
 
 // Primitive set of one node used by the two-point flux.
@@ -100,7 +100,7 @@ struct Prim {
 template <typename T, int DIM>
 __device__ __forceinline__ void prim_from_cons(const T* q, T gg, Prim<T, DIM>& P, T& p) {
   P.rho = q[0];
-  const T inv = T(1) / q[0];
+  const T inv = rcp(q[0]);
   P.v2 = T(0);
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -108,16 +108,16 @@ __device__ __forceinline__ void prim_from_cons(const T* q, T gg, Prim<T, DIM>& P
     P.v2 += P.v[k] * P.v[k];
   }
   p = (gg - T(1)) * (q[DIM + 1] - T(0.5) * P.rho * P.v2);
-  P.beta = T(0.5) * P.rho / p;
+  P.beta = T(0.5) * P.rho * rcp(p);
 }
 
-// Chandrashekar's flux in direction m given rho^ln, 1/beta^ln:
+// Chandrashekar's flux in direction m given the pair averages:
 //   f_rho = rho^ln {v_m};  f_mk = f_rho {v_k} + delta_km {rho} / (2 {beta});
 //   f_E = f_rho (1/(2 (gamma-1) beta^ln) - {|v|^2}/2) + sum_k {v_k} f_mk.
 template <typename T, int DIM>
 __device__ __forceinline__ void ec_flux_from_means(int m, const Prim<T, DIM>& A,
-                                                   const Prim<T, DIM>& B, T rho_ln,
-                                                   T inv_beta_ln, T half_inv_gm1,
+                                                   const Prim<T, DIM>& B,
+                                                   const PairMeans<T>& mn, T half_inv_gm1,
                                                    T* F) {
   T va[DIM];
 #pragma unroll
@@ -125,13 +125,12 @@ __device__ __forceinline__ void ec_flux_from_means(int m, const Prim<T, DIM>& A,
   T vn = va[0];
 #pragma unroll
   for (int k = 1; k < DIM; ++k) vn = (m == k) ? va[k] : vn;
-  const T p_hat = (A.rho + B.rho) / (T(2) * (A.beta + B.beta));
-  const T frho = rho_ln * vn;
+  const T frho = mn.rho_ln * vn;
   F[0] = frho;
-  T fe = frho * (half_inv_gm1 * inv_beta_ln - T(0.25) * (A.v2 + B.v2));
+  T fe = frho * (half_inv_gm1 * mn.inv_beta_ln - T(0.25) * (A.v2 + B.v2));
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    const T fm = frho * va[k] + ((m == k) ? p_hat : T(0));
+    const T fm = frho * va[k] + ((m == k) ? mn.p_hat : T(0));
     F[1 + k] = fm;
     fe += va[k] * fm;
   }

@@ -67,6 +67,14 @@ __device__ __forceinline__ double k_rel(double t) {
   return (1.0 + t) * log1p(t) - t;
 }
 
+// reciprocal: hardware estimate + two Newton steps (full double precision)
+__device__ __forceinline__ double rcp_d(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
 template <int G>
 __device__ __forceinline__ double seg_sum(double x) {
 #pragma unroll
@@ -97,7 +105,7 @@ __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const R
   const int k = blockIdx.x * C::EPB + wave * C::SEGS + seg;
   const bool valid = k < mp.ne;
   const long long Ntot = (long long)mp.ne * ND;
-  const double gg = mp.gg, gm1 = gg - 1.0;
+  const double gg = mp.gg, gm1 = gg - 1.0, inv_gm1 = 1.0 / gm1;
 
   // per-node constants along the relaxation line
   double rho[NPL], mom[NPL][DIM], ene[NPL], dr[NPL], dm[NPL][DIM], dE[NPL];
@@ -127,13 +135,13 @@ __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const R
       ene[j] = 1.0;
       dE[j] = 0.0;
     }
-    invrho[j] = 1.0 / rho[j];
+    invrho[j] = rcp_d(rho[j]);
     double mm = 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) mm += mom[j][d] * mom[j][d];
     m2[j] = mm;
     const double p = gm1 * (ene[j] - 0.5 * mm * invrho[j]);
-    invp[j] = 1.0 / p;
+    invp[j] = rcp_d(p);
     beta[j] = 0.5 * rho[j] * invp[j];
     double M = 1.0;
     {
@@ -149,7 +157,7 @@ __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const R
     // w(u_old).du and its round-off scale
     const double s_phys = log(p) - gg * log(rho[j]);
     const double v2 = mm * invrho[j] * invrho[j];
-    double t = ((gg - s_phys) / gm1 - beta[j] * v2) * dr[j];
+    double t = ((gg - s_phys) * inv_gm1 - beta[j] * v2) * dr[j];
     double sc = fabs(t);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -170,9 +178,10 @@ __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const R
   const double noise = 64.0 * DBL_EPSILON * (scale + fabs(deta));
 
   // relative entropy sum B(g) and admissibility along the line
+  // (an inadmissible node makes the element sum +INF)
   auto Bsum = [&](double g, bool& ok) -> double {
     double part = 0.0;
-    double bad = 0.0;
+    bool bad = false;
 #pragma unroll
     for (int j = 0; j < NPL; ++j) {
       const double r0 = rho[j];
@@ -185,13 +194,13 @@ __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const R
         mdm += mom[j][d] * dmg;
         dm2 += dmg * dmg;
       }
-      const double q = 1.0 / (r0 * r1);
+      const double q = rcp_d(r0 * r1);
       const double dke = (r0 * (2.0 * mdm + dm2) - drg * m2[j]) * q;
       const double dp = gm1 * (g * dE[j] - 0.5 * dke);
       const double tr = drg * invrho[j];
       const double tp = dp * invp[j];
       const bool okn = (r1 > 0.0) && (1.0 + tp > 0.0);
-      if (!okn && has[j]) bad += 1.0;
+      if (!okn && has[j]) bad = true;
       double Dn = 0.0;
       if (okn) {
         const double tz = (tp - tr) * r0 * r0 * q;
@@ -201,13 +210,12 @@ __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const R
           const double dv = (g * dm[j][d] - drg * mom[j][d] * invrho[j]) * r0 * q;
           dv2 += dv * dv;
         }
-        Dn = r1 * h_rel(tz) / gm1 + r0 * k_rel(tr) + beta[j] * r1 * dv2;
+        Dn = r1 * h_rel(tz) * inv_gm1 + r0 * k_rel(tr) + beta[j] * r1 * dv2;
       }
       part += Mi[j] * Dn;
     }
-    part = seg_sum<G>(part);
-    bad = seg_sum<G>(bad);
-    ok = bad == 0.0;
+    part = seg_sum<G>(bad ? INFINITY : part);
+    ok = !isinf(part);
     return part;
   };
 

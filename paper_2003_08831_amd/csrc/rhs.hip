@@ -24,6 +24,27 @@
 #include "device_math.h"
 #include "internal.h"
 
+// Tuning knobs (compile-time): the number of line tasks a block is sized for
+// (elements per block = max(1, target / tasks per element)), capped by an LDS
+// budget in KiB, and the minimum waves per SIMD requested from the register
+// allocator (0 = compiler's choice).  One wavefront of tasks per block measured
+// fastest: a single-wave block needs no cross-wave barrier waits and many
+// small blocks overlap each other's memory latency.
+#ifndef ESRK_RHS_TARGET_TASKS
+#define ESRK_RHS_TARGET_TASKS 64
+#endif
+#ifndef ESRK_RHS_LDS_KB
+#define ESRK_RHS_LDS_KB 64
+#endif
+#ifndef ESRK_RHS_WAVES_PER_EU
+#define ESRK_RHS_WAVES_PER_EU 0
+#endif
+// 1: load the interface states before the volume pairs (latency hiding, more
+// registers); 0: load them just before the interface fluxes.
+#ifndef ESRK_RHS_EARLY_FACE_LOADS
+#define ESRK_RHS_EARLY_FACE_LOADS 0
+#endif
+
 namespace esrk {
 
 template <int DIM, int N>
@@ -37,13 +58,16 @@ struct Geo {
 template <int DIM, int N, typename T>
 struct RhsCfg {
   using G = Geo<DIM, N>;
-  static constexpr int NP = DIM + 6;
-  static constexpr int IR = 0, IV = 1, IB = DIM + 1, ILR = DIM + 2, ILB = DIM + 3,
-                       IV2 = DIM + 4, IC = DIM + 5;
+  static constexpr int NP = DIM + 3;  // rho, v[DIM], beta, |v|^2
+  static constexpr int IR = 0, IV = 1, IB = DIM + 1, IV2 = DIM + 2;
+  // LDS slot of node i: i + i/N, so that lines along any direction spread
+  // over the banks (element stride NDP)
+  static constexpr int NDP = G::ND + G::ND / N;
   static constexpr int LDS_PER_ELEM =
-      G::ND * (int)((NP + DIM * G::NV) * sizeof(T) + sizeof(double));
-  static constexpr int BUDGET = 64 * 1024;
-  static constexpr int E_TASK = (256 / G::TASKS) > 0 ? 256 / G::TASKS : 1;
+      NDP * (int)((NP + DIM * G::NV) * sizeof(T)) + G::ND * (int)sizeof(double);
+  static constexpr int BUDGET = ESRK_RHS_LDS_KB * 1024;
+  static constexpr int E_TASK =
+      (ESRK_RHS_TARGET_TASKS / G::TASKS) > 0 ? ESRK_RHS_TARGET_TASKS / G::TASKS : 1;
   static constexpr int E_LDS = (BUDGET / LDS_PER_ELEM) > 0 ? BUDGET / LDS_PER_ELEM : 1;
   static constexpr int E = E_TASK < E_LDS ? E_TASK : E_LDS;
   static constexpr int RAW = E * G::TASKS;
@@ -71,24 +95,22 @@ __device__ __forceinline__ int neighbour(const MeshParams& mp, int k, int m, int
   return c[0] + mp.nel[0] * (c[1] + mp.nel[1] * c[2]);
 }
 
-// Interface flux f* in direction m between left state qL and right state qR.
+// Interface flux f* in direction m between a left and a right node, given
+// both primitive sets and conserved states.
 template <typename T, int DIM>
-__device__ __forceinline__ void interface_flux(int m, const T* qL, const T* qR, T gg,
+__device__ __forceinline__ void interface_flux(int m, const Prim<T, DIM>& A, const T* qL,
+                                               const Prim<T, DIM>& B, const T* qR, T gg,
                                                T half_inv_gm1, T lam_scale, T* F) {
-  Prim<T, DIM> A, B;
-  T pA, pB;
-  prim_from_cons<T, DIM>(qL, gg, A, pA);
-  prim_from_cons<T, DIM>(qR, gg, B, pB);
-  const T rho_ln = logmean_direct(A.rho, B.rho);
-  const T ibl = inv_logmean_direct(A.beta, B.beta);
-  ec_flux_from_means<T, DIM>(m, A, B, rho_ln, ibl, half_inv_gm1, F);
+  const PairMeans<T> mn = pair_means(A.rho, B.rho, A.beta, B.beta);
+  ec_flux_from_means<T, DIM>(m, A, B, mn, half_inv_gm1, F);
   T vA = A.v[0], vB = B.v[0];
 #pragma unroll
   for (int k = 1; k < DIM; ++k) {
     vA = (m == k) ? A.v[k] : vA;
     vB = (m == k) ? B.v[k] : vB;
   }
-  const T cA = sqrt(gg * pA / A.rho), cB = sqrt(gg * pB / B.rho);
+  // c^2 = gamma p / rho = gamma / (2 beta)
+  const T cA = sqrt(T(0.5) * gg * rcp(A.beta)), cB = sqrt(T(0.5) * gg * rcp(B.beta));
   const T sA = fabs(vA) + cA, sB = fabs(vB) + cB;
   const T lam = sA > sB ? sA : sB;
   const T hl = T(0.5) * lam_scale * lam;
@@ -98,13 +120,18 @@ __device__ __forceinline__ void interface_flux(int m, const T* qL, const T* qR, 
 
 template <int DIM, int N, typename T>
 __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
+#if ESRK_RHS_WAVES_PER_EU > 0
+    __attribute__((amdgpu_waves_per_eu(ESRK_RHS_WAVES_PER_EU)))
+#endif
     rhs_kernel(const MeshParams mp, const RhsArgs a) {
   using C = RhsCfg<DIM, N, T>;
   using G = Geo<DIM, N>;
-  constexpr int ND = G::ND, NV = G::NV, NP = C::NP, E = C::E, EN = E * ND;
+  constexpr int ND = G::ND, NV = G::NV, NP = C::NP, E = C::E, NDP = C::NDP;
+  constexpr int EN = E * ND;    // nodes per block
+  constexpr int ENP = E * NDP;  // padded LDS slots per field
   constexpr int TH = C::THREADS;
-  __shared__ T sp[NP * EN];
-  __shared__ T sacc[DIM * NV * EN];
+  __shared__ T sp[NP * ENP];
+  __shared__ T sacc[DIM * NV * ENP];
   __shared__ double sred[EN];
 
   const int tid = threadIdx.x;
@@ -127,6 +154,8 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
   // ---- phase 0: node primitives into LDS ----
   for (int idx = tid; idx < EN; idx += TH) {
     const int e = idx / ND;
+    const int i = idx - e * ND;
+    const int slot = e * NDP + i + i / N;
     const int k = k0 + e;
     T q[NV];
     if (k < mp.ne) {
@@ -145,17 +174,13 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
     if (!(P.rho > T(0)) || !(p > T(0))) {
       if (k < mp.ne) latch(a.scal, ESRK_ENONPHYS, k);
       P.rho = T(1);
-      p = T(1);
       P.beta = T(0.5);
     }
-    sp[C::IR * EN + idx] = P.rho;
+    sp[C::IR * ENP + slot] = P.rho;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) sp[(C::IV + d) * EN + idx] = P.v[d];
-    sp[C::IB * EN + idx] = P.beta;
-    sp[C::ILR * EN + idx] = log(P.rho);
-    sp[C::ILB * EN + idx] = log(P.beta);
-    sp[C::IV2 * EN + idx] = P.v2;
-    sp[C::IC * EN + idx] = sqrt(gg * p / P.rho);
+    for (int d = 0; d < DIM; ++d) sp[(C::IV + d) * ENP + slot] = P.v[d];
+    sp[C::IB * ENP + slot] = P.beta;
+    sp[C::IV2 * ENP + slot] = P.v2;
   }
   __syncthreads();
 
@@ -169,20 +194,38 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
     if (k >= mp.ne) continue;
     const int stride = (m == 0) ? 1 : (m == 1) ? N : N * N;
     const int base = (l % stride) + (l / stride) * stride * N;
-    const int eo = e * ND;
+
+    // conserved states on both sides of the two faces of the line:
+    // side 0 = (-m neighbour's last node | own first node),
+    // side 1 = (own last node | +m neighbour's first node)
+    T qL[2][NV], qR[2][NV];
+    auto load_faces = [&]() {
+      const int km = neighbour<DIM>(mp, k, m, -1);
+      const int kp = neighbour<DIM>(mp, k, m, +1);
+      const long long g0L = (long long)km * ND + base + (N - 1) * stride;
+      const long long g0R = (long long)k * ND + base;
+      const long long g1L = (long long)k * ND + base + (N - 1) * stride;
+      const long long g1R = (long long)kp * ND + base;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        qL[0][v] = T(a.y[v * Ntot + g0L]);
+        qR[0][v] = T(a.y[v * Ntot + g0R]);
+        qL[1][v] = T(a.y[v * Ntot + g1L]);
+        qR[1][v] = T(a.y[v * Ntot + g1R]);
+      }
+    };
+    if (ESRK_RHS_EARLY_FACE_LOADS) load_faces();
 
     Prim<T, DIM> P[N];
-    T lr[N], lb[N];
 #pragma unroll
     for (int q = 0; q < N; ++q) {
-      const int idx = eo + base + q * stride;
-      P[q].rho = sp[C::IR * EN + idx];
+      const int node = base + q * stride;
+      const int slot = e * NDP + node + node / N;
+      P[q].rho = sp[C::IR * ENP + slot];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) P[q].v[d] = sp[(C::IV + d) * EN + idx];
-      P[q].beta = sp[C::IB * EN + idx];
-      P[q].v2 = sp[C::IV2 * EN + idx];
-      lr[q] = sp[C::ILR * EN + idx];
-      lb[q] = sp[C::ILB * EN + idx];
+      for (int d = 0; d < DIM; ++d) P[q].v[d] = sp[(C::IV + d) * ENP + slot];
+      P[q].beta = sp[C::IB * ENP + slot];
+      P[q].v2 = sp[C::IV2 * ENP + slot];
     }
     T acc[N][NV];
 #pragma unroll
@@ -194,10 +237,9 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
     for (int p0 = 0; p0 < N; ++p0) {
 #pragma unroll
       for (int p1 = p0 + 1; p1 < N; ++p1) {
-        const T rho_ln = logmean(P[p0].rho, P[p1].rho, lr[p0] - lr[p1]);
-        const T ibl = inv_logmean(P[p0].beta, P[p1].beta, lb[p0] - lb[p1]);
+        const PairMeans<T> mn = pair_means(P[p0].rho, P[p1].rho, P[p0].beta, P[p1].beta);
         T F[NV];
-        ec_flux_from_means<T, DIM>(m, P[p0], P[p1], rho_ln, ibl, half_inv_gm1, F);
+        ec_flux_from_means<T, DIM>(m, P[p0], P[p1], mn, half_inv_gm1, F);
         const T d01 = T(mp.D2[p0 * N + p1]), d10 = T(mp.D2[p1 * N + p0]);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -207,46 +249,43 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
       }
     }
 
-    // interface fluxes at both ends of the line
+    // interface fluxes at both ends of the line.  Both faces go through one
+    // code path (the loop is not unrolled) with identical operands on the two
+    // elements that share a face, so both compute bit-identical f* and the
+    // scheme stays conservative to round-off of the sums.
     const T lam_scale = T(mp.lambda_scale);
     const T iw = T(mp.inv_w_end);
-    {
-      const int kn = neighbour<DIM>(mp, k, m, -1);
-      const long long gin = (long long)kn * ND + base + (N - 1) * stride;
-      const long long gio = (long long)k * ND + base;
-      T qL[NV], qR[NV], F[NV];
+    if (!ESRK_RHS_EARLY_FACE_LOADS) load_faces();
+#pragma unroll 1
+    for (int side = 0; side < 2; ++side) {
+      T ql[NV], qr[NV], F[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        qL[v] = T(a.y[v * Ntot + gin]);
-        qR[v] = T(a.y[v * Ntot + gio]);
+        ql[v] = side ? qL[1][v] : qL[0][v];
+        qr[v] = side ? qR[1][v] : qR[0][v];
       }
-      interface_flux<T, DIM>(m, qL, qR, gg, half_inv_gm1, lam_scale, F);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) acc[0][v] -= iw * F[v];
-    }
-    {
-      const int kn = neighbour<DIM>(mp, k, m, +1);
-      const long long gin = (long long)kn * ND + base;
-      const long long gio = (long long)k * ND + base + (N - 1) * stride;
-      T qL[NV], qR[NV], F[NV];
+      Prim<T, DIM> Pl, Pr;
+      T pl, pr;
+      prim_from_cons<T, DIM>(ql, gg, Pl, pl);
+      prim_from_cons<T, DIM>(qr, gg, Pr, pr);
+      interface_flux<T, DIM>(m, Pl, ql, Pr, qr, gg, half_inv_gm1, lam_scale, F);
+      const T sg = side ? iw : -iw;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        qL[v] = T(a.y[v * Ntot + gio]);
-        qR[v] = T(a.y[v * Ntot + gin]);
+        const T c = sg * F[v];
+        acc[0][v] += side ? T(0) : c;
+        acc[N - 1][v] += side ? c : T(0);
       }
-      interface_flux<T, DIM>(m, qL, qR, gg, half_inv_gm1, lam_scale, F);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) acc[N - 1][v] += iw * F[v];
     }
 
-    const T metric = T(mp.two_over_h[0]);
-    const T metric_m = (m == 0) ? metric
+    const T metric_m = (m == 0) ? T(mp.two_over_h[0])
                                 : (m == 1) ? T(mp.two_over_h[1]) : T(mp.two_over_h[2]);
 #pragma unroll
     for (int q = 0; q < N; ++q) {
-      const int idx = eo + base + q * stride;
+      const int node = base + q * stride;
+      const int slot = e * NDP + node + node / N;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sacc[(m * NV + v) * EN + idx] = metric_m * acc[q][v];
+      for (int v = 0; v < NV; ++v) sacc[(m * NV + v) * ENP + slot] = metric_m * acc[q][v];
     }
   }
   __syncthreads();
@@ -259,6 +298,9 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
     // the first stage publishes the step size for the later stages and the update
     if (a.first && blockIdx.x == 0 && tid == 0) a.scal->dt = dt;
   }
+  const bool want_y = a.stage_mode && a.out && a.sc.beta != 0.0;
+  const bool want_uold = a.stage_mode && a.out;
+  const bool want_du = a.stage_mode && !a.first;
   for (int idx = tid; idx < EN; idx += TH) {
     const int e = idx / ND;
     const int k = k0 + e;
@@ -267,41 +309,43 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
       continue;
     }
     const int i = idx - e * ND;
+    const int slot = e * NDP + i + i / N;
     const long long gi = (long long)k0 * ND + idx;
+    // global operands of the update first (latency hidden by the work below)
+    double uo[NV], yv[NV], dp[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      uo[v] = want_uold ? a.u_old[v * Ntot + gi] : 0.0;
+      yv[v] = (want_y || sizeof(T) != sizeof(double)) ? a.y[v * Ntot + gi] : 0.0;
+      dp[v] = want_du ? a.du[v * Ntot + gi] : 0.0;
+    }
     double kv[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       T s = T(0);
 #pragma unroll
-      for (int m = 0; m < DIM; ++m) s += sacc[(m * NV + v) * EN + idx];
+      for (int m = 0; m < DIM; ++m) s += sacc[(m * NV + v) * ENP + slot];
       kv[v] = -double(s);
     }
     // entropy variables in FP64: w = [(g - s)/(g-1) - beta |v|^2, 2 beta v, -2 beta]
-    double rho, beta, v2, lnr, lnb, vel[DIM];
+    double rho, beta, v2, vel[DIM];
     if constexpr (sizeof(T) == sizeof(double)) {
-      rho = sp[C::IR * EN + idx];
-      beta = sp[C::IB * EN + idx];
-      v2 = sp[C::IV2 * EN + idx];
-      lnr = sp[C::ILR * EN + idx];
-      lnb = sp[C::ILB * EN + idx];
+      rho = sp[C::IR * ENP + slot];
+      beta = sp[C::IB * ENP + slot];
+      v2 = sp[C::IV2 * ENP + slot];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) vel[d] = sp[(C::IV + d) * EN + idx];
+      for (int d = 0; d < DIM; ++d) vel[d] = sp[(C::IV + d) * ENP + slot];
     } else {
-      double q[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) q[v] = a.y[v * Ntot + gi];
       Prim<double, DIM> P;
       double p;
-      prim_from_cons<double, DIM>(q, ggd, P, p);
+      prim_from_cons<double, DIM>(yv, ggd, P, p);
       rho = P.rho;
       beta = P.beta;
       v2 = P.v2;
-      lnr = log(rho);
-      lnb = log(beta);
 #pragma unroll
       for (int d = 0; d < DIM; ++d) vel[d] = P.v[d];
     }
-    (void)rho;
+    const double lnr = log(rho), lnb = log(beta);
     const double s_phys = (1.0 - ggd) * lnr - 0.6931471805599453 - lnb;  // ln p - g ln rho
     double wdot = ((ggd - s_phys) / (ggd - 1.0) - beta * v2) * kv[0];
 #pragma unroll
@@ -324,16 +368,13 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
       if (a.out) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          double y = a.sc.alpha * a.u_old[v * Ntot + gi] + cdt * kv[v];
-          if (a.sc.beta != 0.0) y += a.sc.beta * a.y[v * Ntot + gi];
+          double y = a.sc.alpha * uo[v] + cdt * kv[v];
+          if (want_y) y += a.sc.beta * yv[v];
           a.out[v * Ntot + gi] = y;
         }
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double prev = a.first ? 0.0 : a.du[v * Ntot + gi];
-        a.du[v * Ntot + gi] = prev + bdt * kv[v];
-      }
+      for (int v = 0; v < NV; ++v) a.du[v * Ntot + gi] = dp[v] + bdt * kv[v];
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) a.out[v * Ntot + gi] = kv[v];

@@ -40,3 +40,32 @@ def normwise(g, o, nv):
         sc = np.abs(o[v]).max()
         out.append(np.abs(g[v] - o[v]).max() / (sc if sc > 0 else 1.0))
     return max(out)
+
+
+def term_scale(O, ms, u):
+    """Per-component scale of the terms the right-hand side sums before they
+    cancel: max |f_v,m(u)| over nodes and directions, times the largest
+    metric 2/h_m, times the largest row sum of |2 D| plus the interface lift
+    1/w_0 (all from the oracle's own operators)."""
+    U = np.asarray(u).reshape(ms.nv, -1)
+    fmax = np.zeros(ms.nv)
+    for i in range(U.shape[1]):
+        for m in range(ms.dim):
+            fmax = np.maximum(fmax, np.abs(O.phys_flux(ms.dim, ms.gas_gamma, m, U[:, i])))
+    D = O.dmat(ms.deg)
+    _, w = O.lgl(ms.deg)
+    metric = max(2.0 * ms.nel[m] / (ms.hi[m] - ms.lo[m]) for m in range(ms.dim))
+    opnorm = np.abs(2.0 * D).sum(axis=1).max() + 1.0 / w[0]
+    return fmax * metric * opnorm * ms.dim
+
+
+def rhs_close(g, o, ms, S, rel=1e-12, cond=1e-14):
+    """Component-wise: |g - o| <= rel * max|o_v| + cond * S_v, where S_v is the
+    term scale (FP64 evaluations of a cancelling sum differ by ~eps * S_v)."""
+    g = np.asarray(g).reshape(ms.nv, -1)
+    o = np.asarray(o).reshape(ms.nv, -1)
+    worst = 0.0
+    for v in range(ms.nv):
+        tol = rel * np.abs(o[v]).max() + cond * S[v]
+        worst = max(worst, np.abs(g[v] - o[v]).max() / tol)
+    return worst
