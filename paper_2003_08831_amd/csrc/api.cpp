@@ -28,6 +28,9 @@ struct esrk_ctx {
   double* gamma_k = nullptr;
   int32_t* iters = nullptr;
   double* speed_parts = nullptr;
+  void* theta = nullptr;      // Navier-Stokes: entropy-variable gradients
+  double* visc = nullptr;     // Navier-Stokes: viscous right-hand side
+  double* vdiss = nullptr;    // Navier-Stokes: per-element viscous dissipation
   esrk::RelaxPart* relax_parts = nullptr;
   int n_relax_parts = 0;
   DevScalars* scal = nullptr;
@@ -64,6 +67,21 @@ esrk::RhsArgs base_args(esrk_ctx* c) {
   std::memset(&a, 0, sizeof(a));
   a.scal = c->scal;
   return a;
+}
+
+// Navier-Stokes viscous right-hand side of state y into ctx->visc (no-op for Euler).
+hipError_t viscous(esrk_ctx* x, const double* y, double* diss, hipStream_t s) {
+  if (!(x->cfg.mu > 0.0)) return hipSuccess;
+  esrk::NsArgs n;
+  n.y = y;
+  n.theta = x->theta;
+  n.visc = x->visc;
+  n.diss = diss;
+  n.mu = x->cfg.mu;
+  n.R = x->cfg.gas_r;
+  n.kappa = x->cfg.mu * (x->cfg.gas_gamma * x->cfg.gas_r / (x->cfg.gas_gamma - 1.0)) /
+            x->cfg.prandtl;
+  return esrk::launch_ns(x->mp, x->cfg.precision, n, s);
 }
 
 }  // namespace
@@ -142,6 +160,12 @@ esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
             hipMalloc(&x->iters, ne * sizeof(int32_t)) == hipSuccess &&
             hipMalloc(&x->speed_parts, esrk::kSpeedBlocks * sizeof(double)) == hipSuccess &&
             hipMalloc(&x->scal, sizeof(DevScalars)) == hipSuccess;
+  if (c.mu > 0.0) {
+    const size_t tsz = c.precision == ESRK_FP64 ? sizeof(double) : sizeof(float);
+    ok = ok && hipMalloc(&x->theta, (size_t)c.dim * len * tsz) == hipSuccess &&
+         hipMalloc(&x->visc, len * sizeof(double)) == hipSuccess &&
+         hipMalloc(&x->vdiss, ne * sizeof(double)) == hipSuccess;
+  }
   x->n_relax_parts = esrk::relax_blocks(mp);
   ok = ok && hipMalloc(&x->relax_parts, x->n_relax_parts * sizeof(esrk::RelaxPart)) == hipSuccess;
   if (!ok) {
@@ -169,6 +193,9 @@ void esrk_destroy(esrk_ctx* x) {
   (void)hipFree(x->gamma_k);
   (void)hipFree(x->iters);
   (void)hipFree(x->speed_parts);
+  (void)hipFree(x->theta);
+  (void)hipFree(x->visc);
+  (void)hipFree(x->vdiss);
   (void)hipFree(x->relax_parts);
   (void)hipFree(x->scal);
   delete x;
@@ -193,12 +220,19 @@ esrk_status esrk_rhs_euler(esrk_ctx* x, const double* u, double* dudt, double* e
 
 esrk_status esrk_rhs_ns(esrk_ctx* x, const double* u, double* dudt, double* eta_rate,
                         double* visc_diss, void* stream) {
-  if (!x) return ESRK_EINVAL;
-  if (x->cfg.mu > 0.0) return ESRK_ENOTSUP;
-  esrk_status st = esrk_rhs_euler(x, u, dudt, eta_rate, stream);
-  if (st == ESRK_OK && visc_diss)
-    st = hip_status(hipMemsetAsync(visc_diss, 0, x->ne * sizeof(double), (hipStream_t)stream));
-  return st;
+  if (!x || !u || !dudt || (const double*)dudt == u) return ESRK_EINVAL;
+  if (!(x->cfg.mu > 0.0)) return ESRK_EINVAL;  // Euler contexts use esrk_rhs_euler
+  hipStream_t s = (hipStream_t)stream;
+  x->last = s;
+  hipError_t e = viscous(x, u, visc_diss, s);
+  if (e != hipSuccess) return ESRK_EHIP;
+  esrk::RhsArgs a = base_args(x);
+  a.y = u;
+  a.out = dudt;
+  a.eta = eta_rate;
+  a.visc = x->visc;
+  a.stage_mode = 0;
+  return hip_status(esrk::launch_rhs(x->mp, x->cfg.precision, a, s));
 }
 
 esrk_status esrk_rk_stage(esrk_ctx* x, int stage, double dt, const double* u_old,
@@ -213,7 +247,9 @@ esrk_status esrk_rk_stage(esrk_ctx* x, int stage, double dt, const double* u_old
     return ESRK_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   x->last = s;
+  if (viscous(x, y_in, nullptr, s) != hipSuccess) return ESRK_EHIP;
   esrk::RhsArgs a = base_args(x);
+  a.visc = x->cfg.mu > 0.0 ? x->visc : nullptr;
   a.y = y_in;
   a.u_old = u_old;
   a.out = last ? nullptr : y_out;
@@ -271,7 +307,10 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
   double* bufs[2] = {x->ya, x->yb};
   for (int i = 0; i < x->stages && e == hipSuccess; ++i) {
     const bool last = i == x->stages - 1;
+    e = viscous(x, yin, nullptr, s);
+    if (e != hipSuccess) break;
     esrk::RhsArgs a = base_args(x);
+    a.visc = x->cfg.mu > 0.0 ? x->visc : nullptr;
     a.y = yin;
     a.u_old = u;
     a.out = last ? nullptr : bufs[i & 1];

@@ -58,6 +58,7 @@ struct RhsArgs {
   double* eta;          // plain: eta_rate (nullable); stage: deta accumulator
   const double* dt_dev; // stage mode: device dt (nullable -> dt_host or speed_parts)
   const double* speed_parts;  // stage 0 with CFL step: kSpeedBlocks wave-speed maxima
+  const double* visc;   // nullable: viscous right-hand side added to k (Navier-Stokes)
   double dt_host;
   StageCoef sc;
   int stage_mode;       // 0: plain right-hand side, 1: RK stage
@@ -72,6 +73,16 @@ void lobatto_tables(int deg, double* x, double* w, double* D);
 // Launchers (return hipError_t).
 hipError_t launch_rhs(const MeshParams& mp, int precision, const RhsArgs& a,
                       hipStream_t s);
+
+// BR1 viscous terms: theta (T precision, [dim][nv][N]) and Visc (FP64, [nv][N]).
+struct NsArgs {
+  const double* y;
+  void* theta;
+  double* visc;
+  double* diss;  // nullable, [ne]
+  double mu, kappa, R;
+};
+hipError_t launch_ns(const MeshParams& mp, int precision, const NsArgs& a, hipStream_t s);
 
 struct RelaxArgs {
   const double* u_old;

@@ -326,6 +326,7 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
 #pragma unroll
       for (int m = 0; m < DIM; ++m) s += sacc[(m * NV + v) * ENP + slot];
       kv[v] = -double(s);
+      if (a.visc) kv[v] += a.visc[v * Ntot + gi];
     }
     // entropy variables in FP64: w = [(g - s)/(g-1) - beta |v|^2, 2 beta v, -2 beta]
     double rho, beta, v2, vel[DIM];
