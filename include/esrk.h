@@ -142,6 +142,48 @@ esrk_status esrk_sync_status(esrk_ctx* ctx, int64_t* bad_elem);
 
 const char* esrk_status_str(esrk_status s);
 
+/* ---- Batches of independent simulations ----------------------------------
+ * Many periodic 2-D meshes of different sizes that share degree, physics,
+ * precision and Runge-Kutta method, advanced together: each stage is one
+ * kernel launch over a work list covering every simulation; each simulation
+ * keeps its own CFL step, its own gamma = min over its elements (Sec. 2,
+ * local relaxation theorem, applied per simulation) and its own time.
+ * State layout: one packed device array; simulation s occupies
+ * [esrk_batch_offset(b, s), + (dim+2) * N_s) in the single-mesh layout.
+ * Per-element arrays are packed the same way (esrk_batch_elem_offset). */
+typedef struct esrk_batch esrk_batch;
+
+/* cfgs[0..nsims): 2-D only (ESRK_ENOTSUP otherwise), Euler (mu = 0); dim,
+ * deg, precision, tableau, gas_gamma and lambda_scale must agree (EINVAL);
+ * nel, lo, hi and cfl may differ.  Allocates all workspace. */
+esrk_status esrk_batch_create(const esrk_config* cfgs, int nsims, esrk_batch** out);
+void esrk_batch_destroy(esrk_batch* b);
+int esrk_batch_num_sims(const esrk_batch* b);
+size_t esrk_batch_state_len(const esrk_batch* b);  /* doubles of the packed state */
+size_t esrk_batch_num_elems(const esrk_batch* b);
+size_t esrk_batch_offset(const esrk_batch* b, int sim);
+size_t esrk_batch_elem_offset(const esrk_batch* b, int sim);
+int esrk_batch_tile(const esrk_batch* b);  /* elements per block of the stage kernel */
+
+/* One locally relaxed step of every simulation, in place, with each
+ * simulation's CFL step.  t: device [nsims] (inout); gamma: device [nsims]
+ * (nullable, out).  No host synchronization, no allocation. */
+esrk_status esrk_batch_step(esrk_batch* b, double* u, double* t, double* gamma, void* stream);
+
+/* Times every compiled tile (elements per block) of the stage kernel on the
+ * state u (read only; workspace is overwritten), keeps the fastest and
+ * returns it in *tile_out (nullable).  Synchronizes the stream. */
+esrk_status esrk_batch_autotune(esrk_batch* b, const double* u, int reps, int* tile_out,
+                                void* stream);
+
+/* nsteps batch steps captured once into a hipGraph (re-captured when u, t,
+ * gamma, nsteps, the tile or the stream change) and replayed on `stream`,
+ * which must not be the NULL stream. */
+esrk_status esrk_batch_run_graph(esrk_batch* b, double* u, double* t, double* gamma, int nsteps,
+                                 void* stream);
+
+esrk_status esrk_batch_sync_status(esrk_batch* b, int64_t* bad_elem);
+
 #ifdef __cplusplus
 }
 #endif

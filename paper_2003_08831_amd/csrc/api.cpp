@@ -66,6 +66,8 @@ esrk::RhsArgs base_args(esrk_ctx* c) {
   esrk::RhsArgs a;
   std::memset(&a, 0, sizeof(a));
   a.scal = c->scal;
+  a.dt_store = &c->scal->dt;
+  a.n_speed_parts = esrk::kSpeedBlocks;
   return a;
 }
 

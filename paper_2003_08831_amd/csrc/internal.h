@@ -44,6 +44,37 @@ struct MeshParams {
   double cfl, hmin;
 };
 
+// The per-mesh part of MeshParams (differs between the simulations of a batch).
+struct MeshDims {
+  int ne;
+  int nel[3];
+  double two_over_h[3];
+  double half_h[3];
+  double hmin, cfl;
+};
+__host__ __device__ inline MeshDims dims_of(const MeshParams& mp) {
+  MeshDims d;
+  d.ne = mp.ne;
+  for (int m = 0; m < 3; ++m) {
+    d.nel[m] = mp.nel[m];
+    d.two_over_h[m] = mp.two_over_h[m];
+    d.half_h[m] = mp.half_h[m];
+  }
+  d.hmin = mp.hmin;
+  d.cfl = mp.cfl;
+  return d;
+}
+
+// One simulation of a batch: its mesh, where its arrays start in the packed
+// batch arrays, and its ranges in the per-block partial arrays.
+struct SimParams {
+  MeshDims md;
+  long long base;       // first double of the sim's state in packed [v][k][i] arrays
+  long long elem_base;  // first element of the sim in packed per-element arrays
+  int speed_p0, speed_p1;
+  int relax_p0, relax_p1;
+};
+
 // Runge-Kutta stage coefficients in the two-register form used on the device:
 //   y_{i+1} = alpha_i u_old + beta_i y_i + c_i dt k_i,   du += b_i dt k_i.
 struct StageCoef {
@@ -57,7 +88,10 @@ struct RhsArgs {
   double* du;           // stage mode: increment accumulator
   double* eta;          // plain: eta_rate (nullable); stage: deta accumulator
   const double* dt_dev; // stage mode: device dt (nullable -> dt_host or speed_parts)
-  const double* speed_parts;  // stage 0 with CFL step: kSpeedBlocks wave-speed maxima
+  const double* speed_parts;  // stage 0 with CFL step: wave-speed maxima per block
+  int n_speed_parts;
+  double* dt_store;     // first stage: where the step size is published (nullable)
+  long long elem_base;  // added to element indices in error reports
   const double* visc;   // nullable: viscous right-hand side added to k (Navier-Stokes)
   double dt_host;
   StageCoef sc;
@@ -108,5 +142,21 @@ hipError_t launch_speed(const MeshParams& mp, const double* u, double* parts, hi
 hipError_t launch_apply(const MeshParams& mp, double* u, const double* du, double* t,
                         const RelaxPart* parts, int nparts, DevScalars* scal,
                         const double* dt_dev, double* stats_out, hipStream_t s);
+
+// ---- batches of simulations (2-D meshes) ----
+int rhs_batch_tiles(const MeshParams& mp, int precision, int* out);
+hipError_t launch_rhs_batch(const MeshParams& mp, int precision, int tile, const RhsArgs& a,
+                            const SimParams* sims, const int2* items, int nitems,
+                            double* dt_sims, const double* dt_in, int grid, hipStream_t s);
+int relax_batch_epb(const MeshParams& mp);
+hipError_t launch_relax_batch(const MeshParams& mp, const RelaxArgs& a, const SimParams* sims,
+                              const int2* items, int nitems, int grid, hipStream_t s);
+hipError_t launch_speed_batch(const MeshParams& mp, const double* u, const SimParams* sims,
+                              const int2* items, int nitems, int grid, double* parts,
+                              hipStream_t s);
+hipError_t launch_apply_batch(const MeshParams& mp, double* u, const double* du,
+                              const SimParams* sims, const int2* items, int nitems, int grid,
+                              const RelaxPart* parts, DevScalars* scal, const double* dt_sims,
+                              double* t, double* gamma_out, hipStream_t s);
 
 }  // namespace esrk

@@ -94,17 +94,21 @@ struct RelaxCfg {
   static constexpr int EPB = (THREADS / 64) * SEGS;  // elements per block
 };
 
+// One block's work: EPB elements starting at element kb of the mesh md; the
+// block partial goes to a.parts[part].
 template <int DIM, int N>
-__global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const RelaxArgs a) {
+__device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims& md,
+                                            const RelaxArgs& a, const int kb, const int part,
+                                            const long long elem_base) {
   using C = RelaxCfg<DIM, N>;
   constexpr int NV = C::NV, G = C::G, NPL = C::NPL, ND = C::ND;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int seg = lane / G;
   const int sl = lane - seg * G;
-  const int k = blockIdx.x * C::EPB + wave * C::SEGS + seg;
-  const bool valid = k < mp.ne;
-  const long long Ntot = (long long)mp.ne * ND;
+  const int k = kb + wave * C::SEGS + seg;
+  const bool valid = k < md.ne;
+  const long long Ntot = (long long)md.ne * ND;
   const double gg = mp.gg, gm1 = gg - 1.0, inv_gm1 = 1.0 / gm1;
 
   // per-node constants along the relaxation line
@@ -150,7 +154,7 @@ __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const R
       for (int d = 0; d < DIM; ++d) {
         const int im = ii % N;
         ii /= N;
-        M *= mp.half_h[d] * mp.w[im];
+        M *= md.half_h[d] * mp.w[im];
       }
     }
     Mi[j] = has[j] ? M : 0.0;
@@ -241,7 +245,7 @@ __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const R
       if (!(phi0 < 0.0)) {
         gk = 0.0;
         done = true;
-        if (sl == 0) latch_r(a.scal, ESRK_ENOROOT, k);
+        if (sl == 0) latch_r(a.scal, ESRK_ENOROOT, elem_base + k);
         continue;
       }
     }
@@ -315,7 +319,33 @@ __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const R
       p.n_inactive += wi[q];
       p.max_iters = max(p.max_iters, wm[q]);
     }
-    a.parts[blockIdx.x] = p;
+    a.parts[part] = p;
+  }
+}
+
+template <int DIM, int N>
+__global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const RelaxArgs a) {
+  const MeshDims md = dims_of(mp);
+  relax_block<DIM, N>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB, blockIdx.x, 0);
+}
+
+// Batched form over (simulation, first element) items; partial per item.
+template <int DIM, int N>
+__global__ void __launch_bounds__(256)
+    relax_batch_kernel(const MeshParams mp, const RelaxArgs a0, const SimParams* __restrict__ sims,
+                       const int2* __restrict__ items, int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    const SimParams& P = sims[w.x];
+    RelaxArgs a = a0;
+    a.u_old = a0.u_old + P.base;
+    a.du = a0.du + P.base;
+    a.deta = a0.deta + P.elem_base;
+    a.guess = a0.guess ? a0.guess + P.elem_base : nullptr;
+    a.gamma_k = a0.gamma_k + P.elem_base;
+    a.iters = a0.iters ? a0.iters + P.elem_base : nullptr;
+    relax_block<DIM, N>(mp, P.md, a, w.y, it, P.elem_base);
+    __syncthreads();
   }
 }
 
@@ -502,6 +532,118 @@ hipError_t launch_apply(const MeshParams& mp, double* u, const double* du, doubl
   if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(apply_kernel, dim3(blocks), dim3(256), 0, s, u, du, len, t, parts, nparts,
                      scal, dt_dev, stats_out);
+  return hipGetLastError();
+}
+
+// ---- batched relaxation launch (2-D meshes) ----
+int relax_batch_epb(const MeshParams& mp) {
+  switch (mp.n) {
+    case 2: return RelaxCfg<2, 2>::EPB;
+    case 3: return RelaxCfg<2, 3>::EPB;
+    case 4: return RelaxCfg<2, 4>::EPB;
+    case 5: return RelaxCfg<2, 5>::EPB;
+    case 6: return RelaxCfg<2, 6>::EPB;
+  }
+  return 0;
+}
+
+hipError_t launch_relax_batch(const MeshParams& mp, const RelaxArgs& a, const SimParams* sims,
+                              const int2* items, int nitems, int grid, hipStream_t s) {
+  if (mp.dim != 2) return hipErrorInvalidValue;
+  switch (mp.n) {
+    case 2: hipLaunchKernelGGL((relax_batch_kernel<2, 2>), dim3(grid), dim3(256), 0, s, mp, a, sims, items, nitems); break;
+    case 3: hipLaunchKernelGGL((relax_batch_kernel<2, 3>), dim3(grid), dim3(256), 0, s, mp, a, sims, items, nitems); break;
+    case 4: hipLaunchKernelGGL((relax_batch_kernel<2, 4>), dim3(grid), dim3(256), 0, s, mp, a, sims, items, nitems); break;
+    case 5: hipLaunchKernelGGL((relax_batch_kernel<2, 5>), dim3(grid), dim3(256), 0, s, mp, a, sims, items, nitems); break;
+    case 6: hipLaunchKernelGGL((relax_batch_kernel<2, 6>), dim3(grid), dim3(256), 0, s, mp, a, sims, items, nitems); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Batched wave-speed maxima: items (simulation, first node) of 256 nodes each.
+__global__ void __launch_bounds__(256) speed_batch_kernel(const double* u, double gg,
+                                                          const SimParams* __restrict__ sims,
+                                                          const int2* __restrict__ items,
+                                                          int nitems, int nd, double* parts) {
+  __shared__ double sh[4];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    const SimParams& P = sims[w.x];
+    const long long Ntot = (long long)P.md.ne * nd;
+    const long long i = (long long)w.y + threadIdx.x;
+    double best = 0.0;
+    if (i < Ntot) {
+      const double* us = u + P.base;
+      const double rho = us[i];
+      double mm = 0.0, v[2];
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const double m = us[(1 + d) * Ntot + i];
+        v[d] = m / rho;
+        mm += v[d] * m;
+      }
+      const double p = (gg - 1.0) * (us[3 * Ntot + i] - 0.5 * mm);
+      const double c = sqrt(gg * p / rho);
+      best = (fabs(v[0]) + c) + (fabs(v[1]) + c);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off /= 2) best = fmax(best, __shfl_xor(best, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) parts[it] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    __syncthreads();
+  }
+}
+
+hipError_t launch_speed_batch(const MeshParams& mp, const double* u, const SimParams* sims,
+                              const int2* items, int nitems, int grid, double* parts,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(speed_batch_kernel, dim3(grid), dim3(256), 0, s, u, mp.gg, sims, items,
+                     nitems, mp.nd, parts);
+  return hipGetLastError();
+}
+
+// Batched relaxed update: items (simulation, first node) of 256 nodes; every
+// block reduces its simulation's relaxation partials (fixed order).
+__global__ void __launch_bounds__(256) apply_batch_kernel(double* u, const double* du, int nv,
+                                                          const SimParams* __restrict__ sims,
+                                                          const int2* __restrict__ items,
+                                                          int nitems, int nd,
+                                                          const RelaxPart* parts, DevScalars* s,
+                                                          const double* dt_sims, double* t,
+                                                          double* gamma_out) {
+  __shared__ double sh[4];
+  const bool err = s->status != 0;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    const SimParams& P = sims[w.x];
+    double g = INFINITY;
+    for (int q = P.relax_p0 + threadIdx.x; q < P.relax_p1; q += blockDim.x)
+      g = fmin(g, parts[q].gmin);
+    g = block_min256(g, sh);
+    if (isinf(g)) g = 1.0;
+    const long long Ntot = (long long)P.md.ne * nd;
+    const long long i = (long long)w.y + threadIdx.x;
+    if (!err && i < Ntot) {
+      for (int v = 0; v < nv; ++v) {
+        const long long q = P.base + v * Ntot + i;
+        u[q] = u[q] + g * du[q];
+      }
+    }
+    if (w.y == 0 && threadIdx.x == 0) {
+      if (!err) t[w.x] = t[w.x] + g * dt_sims[w.x];
+      if (gamma_out) gamma_out[w.x] = g;
+    }
+  }
+}
+
+hipError_t launch_apply_batch(const MeshParams& mp, double* u, const double* du,
+                              const SimParams* sims, const int2* items, int nitems, int grid,
+                              const RelaxPart* parts, DevScalars* scal, const double* dt_sims,
+                              double* t, double* gamma_out, hipStream_t s) {
+  hipLaunchKernelGGL(apply_batch_kernel, dim3(grid), dim3(256), 0, s, u, du, mp.dim + 2, sims,
+                     items, nitems, mp.nd, parts, scal, dt_sims, t, gamma_out);
   return hipGetLastError();
 }
 

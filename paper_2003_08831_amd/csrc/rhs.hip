@@ -59,7 +59,6 @@ template <int DIM, int N, typename T>
 struct RhsCfg {
   using G = Geo<DIM, N>;
   static constexpr int NP = DIM + 3;  // rho, v[DIM], beta, |v|^2
-  static constexpr int IR = 0, IV = 1, IB = DIM + 1, IV2 = DIM + 2;
   // LDS slot of node i: i + i/N, so that lines along any direction spread
   // over the banks (element stride NDP)
   static constexpr int NDP = G::ND + G::ND / N;
@@ -70,8 +69,19 @@ struct RhsCfg {
       (ESRK_RHS_TARGET_TASKS / G::TASKS) > 0 ? ESRK_RHS_TARGET_TASKS / G::TASKS : 1;
   static constexpr int E_LDS = (BUDGET / LDS_PER_ELEM) > 0 ? BUDGET / LDS_PER_ELEM : 1;
   static constexpr int E = E_TASK < E_LDS ? E_TASK : E_LDS;
+};
+
+// Block shape for E elements per block.
+template <int DIM, int N, typename T, int E>
+struct RhsShape {
+  using G = Geo<DIM, N>;
+  using C = RhsCfg<DIM, N, T>;
+  static constexpr int NP = C::NP, NDP = C::NDP;
+  static constexpr int IR = 0, IV = 1, IB = DIM + 1, IV2 = DIM + 2;
+  static constexpr int EN = E * G::ND, ENP = E * NDP;
   static constexpr int RAW = E * G::TASKS;
   static constexpr int THREADS = ((RAW < 64 ? 64 : RAW) + 63) / 64 * 64;
+  static constexpr int SP = NP * ENP, SACC = DIM * G::NV * ENP;
 };
 
 __device__ __forceinline__ void latch(DevScalars* s, int code, long long elem) {
@@ -80,19 +90,19 @@ __device__ __forceinline__ void latch(DevScalars* s, int code, long long elem) {
 }
 
 template <int DIM>
-__device__ __forceinline__ int neighbour(const MeshParams& mp, int k, int m, int dir) {
+__device__ __forceinline__ int neighbour(const MeshDims& md, int k, int m, int dir) {
   int c[3];
-  c[0] = k % mp.nel[0];
-  c[1] = (k / mp.nel[0]) % mp.nel[1];
-  c[2] = k / (mp.nel[0] * mp.nel[1]);
+  c[0] = k % md.nel[0];
+  c[1] = (k / md.nel[0]) % md.nel[1];
+  c[2] = k / (md.nel[0] * md.nel[1]);
   int cm = (m == 0) ? c[0] : (m == 1) ? c[1] : c[2];
-  const int nm = (m == 0) ? mp.nel[0] : (m == 1) ? mp.nel[1] : mp.nel[2];
+  const int nm = (m == 0) ? md.nel[0] : (m == 1) ? md.nel[1] : md.nel[2];
   cm += dir;
   cm = (cm < 0) ? cm + nm : (cm >= nm ? cm - nm : cm);
   if (m == 0) c[0] = cm;
   if (m == 1) c[1] = cm;
   if (m == 2) c[2] = cm;
-  return c[0] + mp.nel[0] * (c[1] + mp.nel[1] * c[2]);
+  return c[0] + md.nel[0] * (c[1] + md.nel[1] * c[2]);
 }
 
 // Interface flux f* in direction m between a left and a right node, given
@@ -118,37 +128,32 @@ __device__ __forceinline__ void interface_flux(int m, const Prim<T, DIM>& A, con
   for (int v = 0; v < DIM + 2; ++v) F[v] -= hl * (qR[v] - qL[v]);
 }
 
-template <int DIM, int N, typename T>
-__global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
-#if ESRK_RHS_WAVES_PER_EU > 0
-    __attribute__((amdgpu_waves_per_eu(ESRK_RHS_WAVES_PER_EU)))
-#endif
-    rhs_kernel(const MeshParams mp, const RhsArgs a) {
-  using C = RhsCfg<DIM, N, T>;
+// One block's work: E elements starting at element k0 of the mesh md.
+template <int DIM, int N, typename T, int E>
+__device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& md,
+                                          const RhsArgs& a, const int k0, T* sp, T* sacc,
+                                          double* sred, double* s_dt) {
+  using S = RhsShape<DIM, N, T, E>;
+  using C = S;
   using G = Geo<DIM, N>;
-  constexpr int ND = G::ND, NV = G::NV, NP = C::NP, E = C::E, NDP = C::NDP;
-  constexpr int EN = E * ND;    // nodes per block
-  constexpr int ENP = E * NDP;  // padded LDS slots per field
-  constexpr int TH = C::THREADS;
-  __shared__ T sp[NP * ENP];
-  __shared__ T sacc[DIM * NV * ENP];
-  __shared__ double sred[EN];
+  constexpr int ND = G::ND, NV = G::NV, NDP = S::NDP;
+  constexpr int EN = S::EN;    // nodes per block
+  constexpr int ENP = S::ENP;  // padded LDS slots per field
+  constexpr int TH = S::THREADS;
 
   const int tid = threadIdx.x;
-  const int k0 = blockIdx.x * E;
-  const long long Ntot = (long long)mp.ne * ND;
+  const long long Ntot = (long long)md.ne * ND;
   const T gg = T(mp.gg);
   const T half_inv_gm1 = T(0.5) / (gg - T(1));
 
   // CFL step size of the first stage, from the wave-speed partials of the step
   // start state (max is exact, so every block derives the same dt).
-  __shared__ double s_dt;
   if (a.stage_mode && a.speed_parts && tid < 64) {
     double mx = 0.0;
-    for (int q = tid; q < kSpeedBlocks; q += 64) mx = fmax(mx, a.speed_parts[q]);
+    for (int q = tid; q < a.n_speed_parts; q += 64) mx = fmax(mx, a.speed_parts[q]);
 #pragma unroll
     for (int off = 32; off >= 1; off /= 2) mx = fmax(mx, __shfl_xor(mx, off, 64));
-    if (tid == 0) s_dt = mp.cfl * mp.hmin / (double(mp.n) * mx);
+    if (tid == 0) *s_dt = md.cfl * md.hmin / (double(mp.n) * mx);
   }
 
   // ---- phase 0: node primitives into LDS ----
@@ -158,7 +163,7 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
     const int slot = e * NDP + i + i / N;
     const int k = k0 + e;
     T q[NV];
-    if (k < mp.ne) {
+    if (k < md.ne) {
       const long long gi = (long long)k0 * ND + idx;
 #pragma unroll
       for (int v = 0; v < NV; ++v) q[v] = T(a.y[v * Ntot + gi]);
@@ -172,7 +177,7 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
     T p;
     prim_from_cons<T, DIM>(q, gg, P, p);
     if (!(P.rho > T(0)) || !(p > T(0))) {
-      if (k < mp.ne) latch(a.scal, ESRK_ENONPHYS, k);
+      if (k < md.ne) latch(a.scal, ESRK_ENONPHYS, a.elem_base + k);
       P.rho = T(1);
       P.beta = T(0.5);
     }
@@ -191,7 +196,7 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
     const int m = r / G::NL;
     const int l = r - m * G::NL;
     const int k = k0 + e;
-    if (k >= mp.ne) continue;
+    if (k >= md.ne) continue;
     const int stride = (m == 0) ? 1 : (m == 1) ? N : N * N;
     const int base = (l % stride) + (l / stride) * stride * N;
 
@@ -200,8 +205,8 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
     // side 1 = (own last node | +m neighbour's first node)
     T qL[2][NV], qR[2][NV];
     auto load_faces = [&]() {
-      const int km = neighbour<DIM>(mp, k, m, -1);
-      const int kp = neighbour<DIM>(mp, k, m, +1);
+      const int km = neighbour<DIM>(md, k, m, -1);
+      const int kp = neighbour<DIM>(md, k, m, +1);
       const long long g0L = (long long)km * ND + base + (N - 1) * stride;
       const long long g0R = (long long)k * ND + base;
       const long long g1L = (long long)k * ND + base + (N - 1) * stride;
@@ -278,8 +283,8 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
       }
     }
 
-    const T metric_m = (m == 0) ? T(mp.two_over_h[0])
-                                : (m == 1) ? T(mp.two_over_h[1]) : T(mp.two_over_h[2]);
+    const T metric_m = (m == 0) ? T(md.two_over_h[0])
+                                : (m == 1) ? T(md.two_over_h[1]) : T(md.two_over_h[2]);
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       const int node = base + q * stride;
@@ -294,9 +299,9 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
   const double ggd = mp.gg;
   double dt = 0.0;
   if (a.stage_mode) {
-    dt = a.speed_parts ? s_dt : (a.dt_dev ? *a.dt_dev : a.dt_host);
+    dt = a.speed_parts ? *s_dt : (a.dt_dev ? *a.dt_dev : a.dt_host);
     // the first stage publishes the step size for the later stages and the update
-    if (a.first && blockIdx.x == 0 && tid == 0) a.scal->dt = dt;
+    if (a.first && k0 == 0 && tid == 0 && a.dt_store) *a.dt_store = dt;
   }
   const bool want_y = a.stage_mode && a.out && a.sc.beta != 0.0;
   const bool want_uold = a.stage_mode && a.out;
@@ -304,7 +309,7 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
   for (int idx = tid; idx < EN; idx += TH) {
     const int e = idx / ND;
     const int k = k0 + e;
-    if (k >= mp.ne) {
+    if (k >= md.ne) {
       sred[idx] = 0.0;
       continue;
     }
@@ -359,7 +364,7 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
       for (int d = 0; d < DIM; ++d) {
         const int im = ii % N;
         ii /= N;
-        M *= mp.half_h[d] * mp.w[im];
+        M *= md.half_h[d] * mp.w[im];
       }
     }
     sred[idx] = M * wdot;
@@ -384,7 +389,7 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
   __syncthreads();
   if (tid < E) {
     const int k = k0 + tid;
-    if (k < mp.ne && a.eta) {
+    if (k < md.ne && a.eta) {
       double s = 0.0;
       for (int i = 0; i < ND; ++i) s += sred[tid * ND + i];
       if (a.stage_mode) {
@@ -397,11 +402,62 @@ __global__ void __launch_bounds__((RhsCfg<DIM, N, T>::THREADS))
   }
 }
 
+
+template <int DIM, int N, typename T>
+__global__ void __launch_bounds__((RhsShape<DIM, N, T, RhsCfg<DIM, N, T>::E>::THREADS))
+#if ESRK_RHS_WAVES_PER_EU > 0
+    __attribute__((amdgpu_waves_per_eu(ESRK_RHS_WAVES_PER_EU)))
+#endif
+    rhs_kernel(const MeshParams mp, const RhsArgs a) {
+  constexpr int E = RhsCfg<DIM, N, T>::E;
+  using S = RhsShape<DIM, N, T, E>;
+  __shared__ T sp[S::SP];
+  __shared__ T sacc[S::SACC];
+  __shared__ double sred[S::EN];
+  __shared__ double s_dt;
+  const MeshDims md = dims_of(mp);
+  rhs_block<DIM, N, T, E>(mp, md, a, blockIdx.x * E, sp, sacc, sred, &s_dt);
+}
+
+// Batched form: the blocks walk a work list of (simulation, first element)
+// items of many simulations sharing degree and physics but not mesh size.
+// Pointers in a0 point at the packed batch arrays; per-simulation offsets
+// come from sims[].
+template <int DIM, int N, typename T, int E>
+__global__ void __launch_bounds__((RhsShape<DIM, N, T, E>::THREADS))
+    rhs_batch_kernel(const MeshParams mp, const RhsArgs a0, const SimParams* __restrict__ sims,
+                     const int2* __restrict__ items, int nitems, double* dt_sims,
+                     const double* dt_sims_in) {
+  using S = RhsShape<DIM, N, T, E>;
+  __shared__ T sp[S::SP];
+  __shared__ T sacc[S::SACC];
+  __shared__ double sred[S::EN];
+  __shared__ double s_dt;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    const SimParams& P = sims[w.x];
+    RhsArgs a = a0;
+    a.y = a0.y + P.base;
+    a.u_old = a0.u_old ? a0.u_old + P.base : nullptr;
+    a.out = a0.out ? a0.out + P.base : nullptr;
+    a.du = a0.du ? a0.du + P.base : nullptr;
+    a.eta = a0.eta ? a0.eta + P.elem_base : nullptr;
+    a.speed_parts = a0.speed_parts ? a0.speed_parts + P.speed_p0 : nullptr;
+    a.n_speed_parts = P.speed_p1 - P.speed_p0;
+    a.dt_dev = dt_sims_in ? dt_sims_in + w.x : nullptr;
+    a.dt_store = dt_sims ? dt_sims + w.x : nullptr;
+    a.elem_base = P.elem_base;
+    rhs_block<DIM, N, T, E>(mp, P.md, a, w.y, sp, sacc, sred, &s_dt);
+    __syncthreads();
+  }
+}
+
 template <int DIM, int N, typename T>
 static hipError_t launch_one(const MeshParams& mp, const RhsArgs& a, hipStream_t s) {
-  using C = RhsCfg<DIM, N, T>;
-  const int blocks = (mp.ne + C::E - 1) / C::E;
-  hipLaunchKernelGGL((rhs_kernel<DIM, N, T>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
+  constexpr int E = RhsCfg<DIM, N, T>::E;
+  const int blocks = (mp.ne + E - 1) / E;
+  hipLaunchKernelGGL((rhs_kernel<DIM, N, T>), dim3(blocks), dim3(RhsShape<DIM, N, T, E>::THREADS),
+                     0, s, mp, a);
   return hipGetLastError();
 }
 
@@ -427,6 +483,75 @@ hipError_t launch_rhs(const MeshParams& mp, int precision, const RhsArgs& a, hip
     if (mp.dim == 2) return launch_dim<2, float>(mp, a, s);
     if (mp.dim == 3) return launch_dim<3, float>(mp, a, s);
   }
+  return hipErrorInvalidValue;
+}
+
+// ---- batched launch: tile = elements per block (0 = the default for (DIM, N)) ----
+template <int DIM, int N, typename T, int E>
+static hipError_t batch_one(const MeshParams& mp, const RhsArgs& a, const SimParams* sims,
+                            const int2* items, int nitems, double* dt_sims,
+                            const double* dt_in, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((rhs_batch_kernel<DIM, N, T, E>), dim3(grid),
+                     dim3(RhsShape<DIM, N, T, E>::THREADS), 0, s, mp, a, sims, items, nitems,
+                     dt_sims, dt_in);
+  return hipGetLastError();
+}
+
+template <int DIM, int N, typename T>
+static hipError_t batch_tile(const MeshParams& mp, int tile, const RhsArgs& a,
+                             const SimParams* sims, const int2* items, int nitems,
+                             double* dt_sims, const double* dt_in, int grid, hipStream_t s) {
+  constexpr int E0 = RhsCfg<DIM, N, T>::E;
+  constexpr int EH = E0 / 2 > 0 ? E0 / 2 : 1;
+  constexpr int ED = (RhsCfg<DIM, N, T>::LDS_PER_ELEM * 2 * E0 <= 64 * 1024) ? 2 * E0 : E0;
+  if (tile == 0 || tile == E0)
+    return batch_one<DIM, N, T, E0>(mp, a, sims, items, nitems, dt_sims, dt_in, grid, s);
+  if (tile == EH)
+    return batch_one<DIM, N, T, EH>(mp, a, sims, items, nitems, dt_sims, dt_in, grid, s);
+  if (tile == ED)
+    return batch_one<DIM, N, T, ED>(mp, a, sims, items, nitems, dt_sims, dt_in, grid, s);
+  return hipErrorInvalidValue;
+}
+
+template <int DIM, int N, typename T>
+static void tiles_of(int* out) {
+  constexpr int E0 = RhsCfg<DIM, N, T>::E;
+  out[0] = E0 / 2 > 0 ? E0 / 2 : 1;
+  out[1] = E0;
+  out[2] = (RhsCfg<DIM, N, T>::LDS_PER_ELEM * 2 * E0 <= 64 * 1024) ? 2 * E0 : E0;
+}
+
+// Candidate tiles (elements per block) of the batched stage kernel; the
+// middle one is the default.  Batching is compiled for 2-D meshes.
+int rhs_batch_tiles(const MeshParams& mp, int precision, int* out) {
+  if (mp.dim != 2) return 0;
+#define ESRK_TILES(T)                              \
+  switch (mp.n) {                                  \
+    case 2: tiles_of<2, 2, T>(out); return 3;      \
+    case 3: tiles_of<2, 3, T>(out); return 3;      \
+    case 4: tiles_of<2, 4, T>(out); return 3;      \
+    case 5: tiles_of<2, 5, T>(out); return 3;      \
+    case 6: tiles_of<2, 6, T>(out); return 3;      \
+  }
+  if (precision == ESRK_FP64) { ESRK_TILES(double) } else { ESRK_TILES(float) }
+#undef ESRK_TILES
+  return 0;
+}
+
+hipError_t launch_rhs_batch(const MeshParams& mp, int precision, int tile, const RhsArgs& a,
+                            const SimParams* sims, const int2* items, int nitems,
+                            double* dt_sims, const double* dt_in, int grid, hipStream_t s) {
+  if (mp.dim != 2) return hipErrorInvalidValue;
+#define ESRK_BT(T)                                                                               \
+  switch (mp.n) {                                                                                \
+    case 2: return batch_tile<2, 2, T>(mp, tile, a, sims, items, nitems, dt_sims, dt_in, grid, s); \
+    case 3: return batch_tile<2, 3, T>(mp, tile, a, sims, items, nitems, dt_sims, dt_in, grid, s); \
+    case 4: return batch_tile<2, 4, T>(mp, tile, a, sims, items, nitems, dt_sims, dt_in, grid, s); \
+    case 5: return batch_tile<2, 5, T>(mp, tile, a, sims, items, nitems, dt_sims, dt_in, grid, s); \
+    case 6: return batch_tile<2, 6, T>(mp, tile, a, sims, items, nitems, dt_sims, dt_in, grid, s); \
+  }
+  if (precision == ESRK_FP64) { ESRK_BT(double) } else { ESRK_BT(float) }
+#undef ESRK_BT
   return hipErrorInvalidValue;
 }
 

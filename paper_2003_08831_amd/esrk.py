@@ -81,6 +81,28 @@ def load():
     L.esrk_sync_status.restype = st
     L.esrk_status_str.argtypes = [st]
     L.esrk_status_str.restype = C.c_char_p
+    L.esrk_batch_create.argtypes = [C.POINTER(Config), C.c_int, C.POINTER(vp)]
+    L.esrk_batch_create.restype = st
+    L.esrk_batch_destroy.argtypes = [vp]
+    L.esrk_batch_destroy.restype = None
+    L.esrk_batch_num_sims.argtypes = [vp]
+    L.esrk_batch_num_sims.restype = C.c_int
+    for n in ("esrk_batch_state_len", "esrk_batch_num_elems"):
+        getattr(L, n).argtypes = [vp]
+        getattr(L, n).restype = C.c_size_t
+    for n in ("esrk_batch_offset", "esrk_batch_elem_offset"):
+        getattr(L, n).argtypes = [vp, C.c_int]
+        getattr(L, n).restype = C.c_size_t
+    L.esrk_batch_tile.argtypes = [vp]
+    L.esrk_batch_tile.restype = C.c_int
+    L.esrk_batch_step.argtypes = [vp, vp, vp, vp, vp]
+    L.esrk_batch_step.restype = st
+    L.esrk_batch_autotune.argtypes = [vp, vp, C.c_int, C.POINTER(C.c_int), vp]
+    L.esrk_batch_autotune.restype = st
+    L.esrk_batch_run_graph.argtypes = [vp, vp, vp, vp, C.c_int, vp]
+    L.esrk_batch_run_graph.restype = st
+    L.esrk_batch_sync_status.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.esrk_batch_sync_status.restype = st
     _lib = L
     return L
 
@@ -172,4 +194,54 @@ class Context:
     def sync_status(self):
         bad = C.c_int64(-1)
         rc = load().esrk_sync_status(self._h, C.byref(bad))
+        return rc, bad.value
+
+
+class Batch:
+    """Owns one esrk_batch (many 2-D simulations advanced together)."""
+
+    def __init__(self, cfgs):
+        L = load()
+        arr = (Config * len(cfgs))(*cfgs)
+        h = C.c_void_p()
+        _check(L.esrk_batch_create(arr, len(cfgs), C.byref(h)), "esrk_batch_create")
+        self._h = h
+        self.nsims = int(L.esrk_batch_num_sims(h))
+        self.len = int(L.esrk_batch_state_len(h))
+        self.nelems = int(L.esrk_batch_num_elems(h))
+        self.offsets = [int(L.esrk_batch_offset(h, s)) for s in range(self.nsims)]
+        self.elem_offsets = [int(L.esrk_batch_elem_offset(h, s)) for s in range(self.nsims)]
+
+    @property
+    def tile(self):
+        return int(load().esrk_batch_tile(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().esrk_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, u, t, gamma=None, stream=None):
+        _check(load().esrk_batch_step(self._h, _ptr(u), _ptr(t), _ptr(gamma), _stream(stream)),
+               "esrk_batch_step")
+
+    def autotune(self, u, reps=10, stream=None):
+        tile = C.c_int(0)
+        _check(load().esrk_batch_autotune(self._h, _ptr(u), int(reps), C.byref(tile),
+                                          _stream(stream)), "esrk_batch_autotune")
+        return tile.value
+
+    def run_graph(self, u, t, nsteps, gamma=None, stream=None):
+        _check(load().esrk_batch_run_graph(self._h, _ptr(u), _ptr(t), _ptr(gamma), int(nsteps),
+                                           _stream(stream)), "esrk_batch_run_graph")
+
+    def sync_status(self):
+        bad = C.c_int64(-1)
+        rc = load().esrk_batch_sync_status(self._h, C.byref(bad))
         return rc, bad.value
