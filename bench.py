@@ -60,7 +60,7 @@ def run_mode(esrk, I, torch, precision, steps, warmup):
     ctx = esrk.Context(cfg)
     u = torch.as_tensor(I.tgv_state(ms, MACH)).to("cuda")
     t = torch.zeros(1, dtype=torch.float64, device="cuda")
-    stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+    stats = torch.zeros(6, dtype=torch.float64, device="cuda")
     for _ in range(warmup):
         ctx.step(u, t, 0.0, None, stats)
     torch.cuda.synchronize()

@@ -93,9 +93,12 @@ int esrk_num_vars(const esrk_ctx* ctx);
 esrk_status esrk_rhs_euler(esrk_ctx* ctx, const double* u, double* dudt,
                            double* eta_rate, void* stream);
 
-/* dudt = f(u) for Navier-Stokes (Euler part plus BR1 viscous terms with
- * mu > 0).  visc_diss (nullable): sum_i M_i sum_m theta_m,i . g_m,i >= 0.
- * Returns ESRK_ENOTSUP while the viscous kernels are not compiled in. */
+/* dudt = f(u) for Navier-Stokes (Sec. 3.1: Euler part plus the BR1 viscous
+ * terms in entropy variables; the context must have mu > 0, else
+ * ESRK_EINVAL).  eta_rate as for esrk_rhs_euler (it includes the viscous
+ * contribution).  visc_diss (nullable, [num_elems]):
+ * sum_i M_i sum_m theta_m,i . g_m,i >= 0, the element's viscous entropy
+ * dissipation rate.  u and dudt must not alias. */
 esrk_status esrk_rhs_ns(esrk_ctx* ctx, const double* u, double* dudt, double* eta_rate,
                         double* visc_diss, void* stream);
 
@@ -117,7 +120,8 @@ esrk_status esrk_rk_stage(esrk_ctx* ctx, int stage, double dt, const double* u_o
  * solved per element to root_tol; elements whose root is not determinable in
  * FP64 (no curvature above round-off) get +INF.  *gamma (device scalar) =
  * min_k gamma_k, or 1 if every element is inactive.  gamma_guess (nullable,
- * float [num_elems]) seeds the solve; the result does not depend on it beyond
+ * float [num_elems]) seeds the solve: after phi_k(1) it is the next trial
+ * point if it lies in (0, gamma_max]; the result does not depend on it beyond
  * root_tol.  iters (nullable, [num_elems]) receives the number of phi
  * evaluations per element. */
 esrk_status esrk_local_relaxation_solve(esrk_ctx* ctx, const double* u_old,
@@ -129,7 +133,8 @@ esrk_status esrk_local_relaxation_solve(esrk_ctx* ctx, const double* u_old,
  * gamma = min_k gamma_k, u <- u + gamma du, t <- t + gamma dt).  t is a device
  * scalar.  dt > 0 is used as given; dt <= 0 takes dt from the CFL rule on the
  * device.  gamma_k_out (nullable, [num_elems]) and stats_out (nullable, device
- * double[4] = {gamma, dt, t, number of inactive elements}) are written on the
+ * double[6] = {gamma, dt, t, number of inactive elements, largest and total
+ * number of phi evaluations of the root solves}) are written on the
  * device.  If the device detects an error, u and t are left unchanged and the
  * status is latched.  No host synchronization, no allocation. */
 esrk_status esrk_step(esrk_ctx* ctx, double* u, double* t, double dt, double* gamma_k_out,
@@ -183,6 +188,61 @@ esrk_status esrk_batch_run_graph(esrk_batch* b, double* u, double* t, double* ga
                                  void* stream);
 
 esrk_status esrk_batch_sync_status(esrk_batch* b, int64_t* bad_elem);
+
+/* ---- Learned first trial point of the relaxation solve --------------------
+ * A 5 -> 32 -> 32 -> 1 tanh network (FP32) maps element features to a trial
+ * relaxation parameter; the root solve of esrk_local_relaxation_solve always
+ * runs to root_tol afterwards, so the result does not depend on the network
+ * beyond root_tol (Sec. 2 only prescribes solving the scalar equation).
+ * Model vector (float, device, ESRK_MLP_MODEL entries):
+ *   W1[32][5] @0, b1[32] @160, W2[32][32] @192, b2[32] @1216, w3[32] @1248,
+ *   b3 @1280 (ESRK_MLP_TRAINED trained parameters); input normalization
+ *   scale[5] @1281, mean[5] @1286, std[5] @1291; output out_mean @1296,
+ *   out_std @1297.
+ * Raw features of element k: r = [deta_k, eta_k(u_new) - eta_k(u_old), dt,
+ *   max_i sum_m (|v_m| + c), dt * viscous dissipation rate of k];
+ * network input x_j = (asinh(r_j / scale_j) - mean_j) / std_j;
+ * trial point 1 + dt^2 (out_mean + out_std * y). */
+#define ESRK_MLP_TRAINED 1281
+#define ESRK_MLP_MODEL 1298
+
+/* esrk_local_relaxation_solve with the learned first trial point (model,
+ * nullable) and the raw features written to feats (nullable, float
+ * [num_elems][5]) for training.  visc_rate (nullable, [num_elems]): the
+ * element viscous dissipation rate used as the fifth feature. */
+esrk_status esrk_local_relaxation_solve_ml(esrk_ctx* ctx, const double* u_old,
+                                           const double* du, const double* deta, double dt,
+                                           const double* visc_rate, const float* model,
+                                           float* feats, double* gamma_k, double* gamma,
+                                           int32_t* iters, void* stream);
+
+/* Model used by esrk_step for the first trial point (NULL: none) and a
+ * device buffer (nullable, float [num_elems][5]) that every following
+ * esrk_step fills with the raw features of its elements.  Both pointers are
+ * kept; the caller keeps them alive while they are set. */
+esrk_status esrk_set_step_model(esrk_ctx* ctx, const float* model, float* feats_out);
+
+/* Normalization of B logged samples for training: raw (float [B][5], raw
+ * features as above), gamma (nullable, double [B], their solved relaxation
+ * parameters; inactive elements must be left out).  fit != 0 first sets the
+ * model's normalization entries from the samples: scale_j = mean |r_j|,
+ * mean_j / std_j of asinh(r_j / scale_j), out_mean / out_std of
+ * q = (gamma - 1) / dt^2.  Then x_norm[B][5] (network inputs) and, with gamma,
+ * t_norm[B] = (q - out_mean) / out_std are written.  One workgroup. */
+esrk_status esrk_mlp_prepare(float* model, const float* raw, const double* gamma, int B, int fit,
+                             float* x_norm, float* t_norm, void* stream);
+
+/* Network on normalized inputs: y[b] = net(x_norm[b][0..5)), B samples. */
+esrk_status esrk_mlp_forward(const float* model, const float* x_norm, int B, float* y,
+                             void* stream);
+/* grad[ESRK_MLP_TRAINED] of L = (1/B) sum_b (net(x_b) - t_b)^2 and L (loss,
+ * nullable, device scalar); one workgroup, deterministic summation order. */
+esrk_status esrk_mlp_grad(const float* model, const float* x_norm, const float* t_norm, int B,
+                          float* grad, float* loss, void* stream);
+/* One Adam update (beta1 0.9, beta2 0.999, eps 1e-8) of the trained
+ * parameters; m, v: device moment vectors (zero before step 1). */
+esrk_status esrk_mlp_adam(float* model, const float* grad, float* m, float* v, int step,
+                          float lr, void* stream);
 
 #ifdef __cplusplus
 }

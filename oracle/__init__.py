@@ -89,6 +89,11 @@ def lib():
         L.orc_relax_r.restype = C.c_longdouble
         L.orc_step.argtypes = [mp, C.c_int, C.POINTER(RelaxOpts), C.c_double, C.c_double,
                                dp, dp, dp, dp, dp, C.POINTER(C.c_long)]
+        L.orc_mlp_forward.argtypes = [dp, dp, C.c_int, dp]
+        L.orc_mlp_grad.argtypes = [dp, dp, dp, C.c_int, dp, dp]
+        L.orc_mlp_adam.argtypes = [dp, dp, dp, dp, C.c_int, C.c_double]
+        L.orc_mlp_prepare.argtypes = [dp, dp, dp, C.c_int, C.c_int, dp, dp]
+        L.orc_elem_max_speed.argtypes = [mp, dp, dp]
         _lib = L
     return _lib
 
@@ -287,3 +292,56 @@ def step(m: Mesh, tab, u, t, cfl=0.5, dt=0.0, opts: RelaxOpts | None = None):
                         C.byref(tt), C.byref(gam), _p(gk), C.byref(dtu), C.byref(bad))
     return dict(t=tt.value, gamma=gam.value, gamma_k=gk, dt=dtu.value, rc=rc,
                 bad_elem=bad.value)
+
+
+MLP_PARAMS = 1281
+
+
+def mlp_forward(params, X):
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 5)
+    Y = np.zeros(X.shape[0])
+    assert lib().orc_mlp_forward(_p(params), _p(X), X.shape[0], _p(Y)) == 0
+    return Y
+
+
+def mlp_grad(params, X, T):
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 5)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    g = np.zeros(MLP_PARAMS)
+    loss = C.c_double(0.0)
+    assert lib().orc_mlp_grad(_p(params), _p(X), _p(T), X.shape[0], _p(g), C.byref(loss)) == 0
+    return g, loss.value
+
+
+MLP_MODEL = 1298
+
+
+def mlp_adam(params, grad, m, v, step, lr):
+    """In place on params, m, v (float64 arrays)."""
+    for a in (params, grad, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    assert lib().orc_mlp_adam(_p(params), _p(grad), _p(m), _p(v), int(step), float(lr)) == 0
+
+
+def mlp_prepare(model, raw, gamma=None, fit=False):
+    """Returns (model', x_norm, t_norm or None); model' is a fitted copy."""
+    model = np.array(model, dtype=np.float64)
+    raw = np.ascontiguousarray(raw, dtype=np.float64).reshape(-1, 5)
+    B = raw.shape[0]
+    xn = np.zeros((B, 5))
+    tn = None
+    if gamma is not None:
+        gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+        tn = np.zeros(B)
+    assert lib().orc_mlp_prepare(_p(model), _p(raw), _p(gamma), B, int(bool(fit)), _p(xn),
+                                 _p(tn)) == 0
+    return model, xn, tn
+
+
+def elem_max_speed(m: Mesh, u):
+    ne = lib().orc_num_elems(C.byref(m))
+    s = np.zeros(ne)
+    assert lib().orc_elem_max_speed(C.byref(m), _p(np.ascontiguousarray(u)), _p(s)) == 0
+    return s

@@ -7,7 +7,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["sbp.c", "euler.c", "semidisc.c", "rk.c", "relax.c"]
+SOURCES = ["sbp.c", "euler.c", "semidisc.c", "rk.c", "relax.c", "mlp.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -123,6 +123,22 @@ int orc_step(const orc_mesh* g, int tableau, const orc_relax_opts* o, double cfl
              double dt, double* u, double* t, double* gamma, double* gamma_k,
              double* dt_used, long* bad_elem);
 
+/* ---- network proposing initial relaxation parameters (mlp.c) ---- */
+#define ORC_MLP_PARAMS 1281
+/* Y[b] = network(X[b][0..5)) */
+int orc_mlp_forward(const double* params, const double* X, int B, double* Y);
+/* grad[ORC_MLP_PARAMS] = dL/dparams, L = mean_b (Y[b] - T[b])^2 (also returned) */
+int orc_mlp_grad(const double* params, const double* X, const double* T, int B, double* grad,
+                 double* loss);
+/* One Adam update of params[ORC_MLP_PARAMS] (beta1 0.9, beta2 0.999, eps 1e-8). */
+int orc_mlp_adam(double* params, const double* grad, double* m, double* v, int step, double lr);
+/* Sample normalization; model holds ORC_MLP_MODEL entries (see mlp.c). */
+#define ORC_MLP_MODEL 1298
+int orc_mlp_prepare(double* model, const double* raw, const double* gamma, int B, int fit,
+                    double* xn, double* tn);
+/* smax[k] = max over the nodes of element k of sum_m (|v_m| + c) */
+int orc_elem_max_speed(const orc_mesh* g, const double* u, double* smax);
+
 #ifdef __cplusplus
 }
 #endif

@@ -427,6 +427,21 @@ int orc_elem_entropy(const orc_mesh* g, const double* u, double* eta) {
   return ORC_OK;
 }
 
+int orc_elem_max_speed(const orc_mesh* g, const double* u, double* smax) {
+  geom G;
+  if (setup(g, &G)) return ORC_EINVAL;
+  for (long k = 0; k < G.ne; ++k) {
+    double s = 0.0;
+    for (int i = 0; i < G.nd; ++i) {
+      double ui[5];
+      gather(&G, u, k * G.nd + i, ui);
+      s = fmax(s, orc_wave_speed(G.dim, g->gas_gamma, ui));
+    }
+    smax[k] = s;
+  }
+  return ORC_OK;
+}
+
 double orc_cfl_dt(const orc_mesh* g, const double* u, double cfl) {
   geom G;
   if (setup(g, &G)) return NAN;

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libesrk.so")
-SOURCES = ["api.cpp", "batch.cpp", "tables.cpp", "rhs.hip", "relax.hip", "ns.hip"]
+SOURCES = ["api.cpp", "batch.cpp", "tables.cpp", "rhs.hip", "relax.hip", "ns.hip", "mlp.hip"]
 
 HIPFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -34,6 +34,8 @@ struct esrk_ctx {
   esrk::RelaxPart* relax_parts = nullptr;
   int n_relax_parts = 0;
   DevScalars* scal = nullptr;
+  const float* step_model = nullptr;  // network used by esrk_step for first trial points
+  float* step_feats = nullptr;        // raw features written by esrk_step (nullable)
   hipStream_t last = nullptr;
 };
 
@@ -269,6 +271,7 @@ static esrk::RelaxArgs relax_args(esrk_ctx* x, const double* u_old, const double
                                   const double* deta, const float* guess, double* gk,
                                   int32_t* iters) {
   esrk::RelaxArgs r;
+  std::memset(&r, 0, sizeof(r));
   r.u_old = u_old;
   r.du = du;
   r.deta = deta;
@@ -309,7 +312,7 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
   double* bufs[2] = {x->ya, x->yb};
   for (int i = 0; i < x->stages && e == hipSuccess; ++i) {
     const bool last = i == x->stages - 1;
-    e = viscous(x, yin, nullptr, s);
+    e = viscous(x, yin, x->vdiss, s);
     if (e != hipSuccess) break;
     esrk::RhsArgs a = base_args(x);
     a.visc = x->cfg.mu > 0.0 ? x->visc : nullptr;
@@ -331,12 +334,71 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
     yin = bufs[i & 1];
   }
   double* gk = gamma_k_out ? gamma_k_out : x->gamma_k;
-  if (e == hipSuccess)
-    e = esrk::launch_relax(x->mp, relax_args(x, u, x->du, x->deta, nullptr, gk, x->iters), s);
+  if (e == hipSuccess) {
+    esrk::RelaxArgs r = relax_args(x, u, x->du, x->deta, nullptr, gk, x->iters);
+    r.model = x->step_model;
+    r.feats = x->step_feats;
+    r.dt_dev = &x->scal->dt;
+    r.vfeat = x->cfg.mu > 0.0 ? x->vdiss : nullptr;
+    e = esrk::launch_relax(x->mp, r, s);
+  }
   if (e == hipSuccess)
     e = esrk::launch_apply(x->mp, u, x->du, t, x->relax_parts, x->n_relax_parts, x->scal,
                            &x->scal->dt, stats_out, s);
   return hip_status(e);
+}
+
+esrk_status esrk_local_relaxation_solve_ml(esrk_ctx* x, const double* u_old, const double* du,
+                                           const double* deta, double dt,
+                                           const double* visc_rate, const float* model,
+                                           float* feats, double* gamma_k, double* gamma,
+                                           int32_t* iters, void* stream) {
+  if (!x || !u_old || !du || !deta || !gamma_k || !gamma || !(dt > 0.0)) return ESRK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  x->last = s;
+  esrk::RelaxArgs r = relax_args(x, u_old, du, deta, nullptr, gamma_k, iters);
+  r.model = model;
+  r.feats = feats;
+  r.vfeat = visc_rate;
+  r.dt_host = dt;
+  hipError_t e = esrk::launch_relax(x->mp, r, s);
+  if (e == hipSuccess)
+    e = esrk::launch_relax_finish(x->relax_parts, x->n_relax_parts, x->scal, gamma, s);
+  return hip_status(e);
+}
+
+esrk_status esrk_set_step_model(esrk_ctx* x, const float* model, float* feats_out) {
+  if (!x) return ESRK_EINVAL;
+  x->step_model = model;
+  x->step_feats = feats_out;
+  return ESRK_OK;
+}
+
+esrk_status esrk_mlp_prepare(float* model, const float* raw, const double* gamma, int B, int fit,
+                             float* x_norm, float* t_norm, void* stream) {
+  if (!model || B < 0 || (B > 0 && (!raw || !x_norm))) return ESRK_EINVAL;
+  if (gamma && !t_norm) return ESRK_EINVAL;
+  return hip_status(esrk::launch_mlp_prepare(model, raw, gamma, B, fit, x_norm, t_norm,
+                                             (hipStream_t)stream));
+}
+
+esrk_status esrk_mlp_forward(const float* model, const float* x_norm, int B, float* y,
+                             void* stream) {
+  if (!model || B < 0 || (B > 0 && (!x_norm || !y))) return ESRK_EINVAL;
+  return hip_status(esrk::launch_mlp_forward(model, x_norm, B, y, (hipStream_t)stream));
+}
+
+esrk_status esrk_mlp_grad(const float* model, const float* x_norm, const float* t_norm, int B,
+                          float* grad, float* loss, void* stream) {
+  if (!model || !x_norm || !t_norm || B < 1 || !grad) return ESRK_EINVAL;
+  return hip_status(esrk::launch_mlp_grad(model, x_norm, t_norm, B, grad, loss,
+                                          (hipStream_t)stream));
+}
+
+esrk_status esrk_mlp_adam(float* model, const float* grad, float* m, float* v, int step,
+                          float lr, void* stream) {
+  if (!model || !grad || !m || !v || step < 1 || !(lr > 0.f)) return ESRK_EINVAL;
+  return hip_status(esrk::launch_mlp_adam(model, grad, m, v, step, lr, (hipStream_t)stream));
 }
 
 esrk_status esrk_sync_status(esrk_ctx* x, int64_t* bad_elem) {

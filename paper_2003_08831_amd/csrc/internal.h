@@ -12,6 +12,14 @@ namespace esrk {
 
 constexpr int kMaxN = 6;  // degree <= 5
 
+// Network proposing relaxation parameters (mlp.hip): layout of the model vector.
+constexpr int kMlpIn = 5, kMlpH = 32;
+constexpr int kOffW1 = 0, kOffB1 = 160, kOffW2 = 192, kOffB2 = 1216, kOffW3 = 1248, kOffB3 = 1280;
+constexpr int kMlpTrained = 1281;
+constexpr int kOffScale = 1281, kOffMean = 1286, kOffStd = 1291, kOffOutMean = 1296,
+              kOffOutStd = 1297;
+constexpr int kMlpModel = 1298;
+
 // Device-resident scalars of one context.
 struct DevScalars {
   double dt;           // step size of the current step
@@ -28,6 +36,7 @@ struct RelaxPart {
   double gmin;      // min over the block's elements of gamma_k (+INF if none)
   int n_inactive;   // elements with gamma_k = +INF
   int max_iters;    // largest number of phi evaluations
+  int sum_iters;    // phi evaluations summed over the block's elements
 };
 
 // Mesh + operator tables passed by value to kernels.
@@ -122,7 +131,12 @@ struct RelaxArgs {
   const double* u_old;
   const double* du;
   const double* deta;
-  const float* guess;  // nullable
+  const float* guess;  // nullable: external first trial points
+  const float* model;  // nullable: network proposing the first trial point
+  float* feats;        // nullable: raw network features per element [ne][5]
+  const double* vfeat; // nullable: per-element viscous dissipation rate
+  const double* dt_dev;  // step size for the features (nullable -> dt_host)
+  double dt_host;
   double* gamma_k;
   int32_t* iters;      // nullable
   RelaxPart* parts;    // one per block
@@ -142,6 +156,15 @@ hipError_t launch_speed(const MeshParams& mp, const double* u, double* parts, hi
 hipError_t launch_apply(const MeshParams& mp, double* u, const double* du, double* t,
                         const RelaxPart* parts, int nparts, DevScalars* scal,
                         const double* dt_dev, double* stats_out, hipStream_t s);
+
+// ---- network kernels ----
+hipError_t launch_mlp_forward(const float* p, const float* X, int B, float* Y, hipStream_t s);
+hipError_t launch_mlp_prepare(float* p, const float* raw, const double* gamma, int B, int fit,
+                              float* xn, float* tn, hipStream_t s);
+hipError_t launch_mlp_grad(const float* p, const float* X, const float* T, int B, float* grad,
+                           float* loss, hipStream_t s);
+hipError_t launch_mlp_adam(float* p, const float* g, float* m, float* v, int step, float lr,
+                           hipStream_t s);
 
 // ---- batches of simulations (2-D meshes) ----
 int rhs_batch_tiles(const MeshParams& mp, int precision, int* out);

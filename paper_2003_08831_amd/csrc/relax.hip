@@ -82,6 +82,61 @@ __device__ __forceinline__ double seg_sum(double x) {
   return x;
 }
 
+template <int G>
+__device__ __forceinline__ double seg_max(double x) {
+#pragma unroll
+  for (int off = G / 2; off >= 1; off /= 2) x = fmax(x, __shfl_xor(x, off, 64));
+  return x;
+}
+template <int G>
+__device__ __forceinline__ float seg_sum_f(float x) {
+#pragma unroll
+  for (int off = G / 2; off >= 1; off /= 2) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Network output for the element of this segment (all G lanes take part; the
+// raw features r are the same on every lane of the segment).  Hidden unit j
+// is held by lane j mod G; layer 2 gathers layer-1 values by shuffles.
+template <int G>
+__device__ __forceinline__ float mlp_segment(const float* __restrict__ p, const double* r,
+                                             int seg_base, int sl) {
+  constexpr int U = (kMlpH + G - 1) / G;
+  float x[kMlpIn];
+#pragma unroll
+  for (int i = 0; i < kMlpIn; ++i)
+    x[i] = (asinhf(float(r[i]) / p[kOffScale + i]) - p[kOffMean + i]) / p[kOffStd + i];
+  float h1[U], s2[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = sl + u * G;
+    float s = 0.f;
+    if (j < kMlpH) {
+      s = p[kOffB1 + j];
+#pragma unroll
+      for (int i = 0; i < kMlpIn; ++i) s += p[kOffW1 + j * kMlpIn + i] * x[i];
+    }
+    h1[u] = j < kMlpH ? tanhf(s) : 0.f;
+    s2[u] = j < kMlpH ? p[kOffB2 + j] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < kMlpH; ++i) {
+    const float hi = __shfl(h1[i / G], seg_base + (i % G), 64);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = sl + u * G;
+      if (j < kMlpH) s2[u] += p[kOffW2 + j * kMlpH + i] * hi;
+    }
+  }
+  float y = 0.f;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = sl + u * G;
+    if (j < kMlpH) y += p[kOffW3 + j] * tanhf(s2[u]);
+  }
+  return seg_sum_f<G>(y) + p[kOffB3];
+}
+
 template <int DIM, int N>
 struct RelaxCfg {
   static constexpr int ND = (DIM == 1) ? N : (DIM == 2) ? N * N : N * N * N;
@@ -96,7 +151,7 @@ struct RelaxCfg {
 
 // One block's work: EPB elements starting at element kb of the mesh md; the
 // block partial goes to a.parts[part].
-template <int DIM, int N>
+template <int DIM, int N, bool NET>
 __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims& md,
                                             const RelaxArgs& a, const int kb, const int part,
                                             const long long elem_base) {
@@ -115,7 +170,8 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
   double rho[NPL], mom[NPL][DIM], ene[NPL], dr[NPL], dm[NPL][DIM], dE[NPL];
   double invrho[NPL], invp[NPL], m2[NPL], beta[NPL], Mi[NPL];
   bool has[NPL];
-  double A = 0.0, scale = 0.0;
+  double A = 0.0, scale = 0.0, smax = 0.0;
+  const bool want_feats = NET && (a.feats != nullptr || a.model != nullptr);
 #pragma unroll
   for (int j = 0; j < NPL; ++j) {
     const int i = sl + j * G;
@@ -174,9 +230,17 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
     sc += fabs(te);
     A += Mi[j] * t;
     scale += Mi[j] * sc;
+    if (want_feats && has[j]) {
+      double sp = 0.0;
+      const double c = sqrt(gg * p * invrho[j]);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sp += fabs(mom[j][d] * invrho[j]) + c;
+      smax = fmax(smax, sp);
+    }
   }
   A = seg_sum<G>(A);
   scale = seg_sum<G>(scale);
+  if (want_feats) smax = seg_max<G>(smax);
   const double deta = valid ? a.deta[k] : 0.0;
   const double phi0 = A - deta;
   const double noise = 64.0 * DBL_EPSILON * (scale + fabs(deta));
@@ -229,9 +293,32 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
   bool hi_known = false, done = !valid;
   int side = 0, its = 0;
   const bool have_guess = a.guess != nullptr;
+  double dtf = 0.0;
+  if (want_feats) dtf = a.dt_dev ? *a.dt_dev : a.dt_host;
+  float net_guess = 1.f;
+  bool first_pass = true;
   while (__any(!done)) {
     bool ok = true;
     const double B = Bsum(done ? 1.0 : g_trial, ok);
+    if (first_pass && want_feats) {
+      // features of the element at gamma = 1 (every lane of the segment holds them)
+      double rf[kMlpIn];
+      rf[0] = deta;
+      rf[1] = A + B;  // eta(u_new) - eta(u_old)
+      rf[2] = dtf;
+      rf[3] = smax;
+      rf[4] = (valid && a.vfeat) ? dtf * a.vfeat[k] : 0.0;
+      if (a.feats && valid && sl == 0) {
+#pragma unroll
+        for (int q = 0; q < kMlpIn; ++q) a.feats[(long long)k * kMlpIn + q] = float(rf[q]);
+      }
+      if (NET && a.model) {
+        const float y = mlp_segment<G>(a.model, rf, seg * G, sl);
+        net_guess = float(1.0 + dtf * dtf * (double(a.model[kOffOutMean]) +
+                                             double(a.model[kOffOutStd]) * double(y)));
+      }
+    }
+    first_pass = false;
     if (done) continue;
     ++its;
     const double f = ok ? phi0 + B / g_trial : INFINITY;
@@ -261,12 +348,20 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
       hi_known = true;
       side = +1;
     }
+    // first trial point after gamma = 1: the network's or the caller's guess
+    // (used on either side of 1), else the regula falsi / doubling step
+    double g0 = -1.0;
+    if (its == 1) {
+      if (NET && a.model) g0 = (double)net_guess;
+      else if (have_guess) g0 = a.guess[k];
+      if (!(g0 > 0.0 && g0 <= gmax)) g0 = -1.0;  // also drops +inf (inactive) and NaN
+    }
     if (!hi_known) {
       if (lo >= gmax) {
         gk = gmax;
         done = true;
       } else {
-        g_trial = fmin(2.0 * lo, gmax);
+        g_trial = (g0 > lo) ? fmin(g0, gmax) : fmin(2.0 * lo, gmax);
       }
       continue;
     }
@@ -277,8 +372,8 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
       continue;
     }
     double g;
-    if (its == 1 && have_guess) {
-      g = (double)a.guess[k];
+    if (g0 > 0.0) {
+      g = g0;
     } else if (isinf(fhi)) {
       g = 0.5 * (lo + hi);
     } else {
@@ -298,35 +393,39 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
   double gl = (leader && !isinf(gk) && gk > 0.0) ? gk : INFINITY;
   int inact = (leader && isinf(gk)) ? 1 : 0;
   int itl = leader ? its : 0;
+  int its_sum = itl;
 #pragma unroll
   for (int off = 32; off >= 1; off /= 2) {
     gl = fmin(gl, __shfl_xor(gl, off, 64));
     inact += __shfl_xor(inact, off, 64);
     itl = max(itl, __shfl_xor(itl, off, 64));
+    its_sum += __shfl_xor(its_sum, off, 64);
   }
   __shared__ double wg[C::THREADS / 64];
-  __shared__ int wi[C::THREADS / 64], wm[C::THREADS / 64];
+  __shared__ int wi[C::THREADS / 64], wm[C::THREADS / 64], ws[C::THREADS / 64];
   if (lane == 0) {
     wg[wave] = gl;
     wi[wave] = inact;
     wm[wave] = itl;
+    ws[wave] = its_sum;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    RelaxPart p{INFINITY, 0, 0};
+    RelaxPart p{INFINITY, 0, 0, 0};
     for (int q = 0; q < C::THREADS / 64; ++q) {
       p.gmin = fmin(p.gmin, wg[q]);
       p.n_inactive += wi[q];
       p.max_iters = max(p.max_iters, wm[q]);
+      p.sum_iters += ws[q];
     }
     a.parts[part] = p;
   }
 }
 
-template <int DIM, int N>
+template <int DIM, int N, bool NET>
 __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const RelaxArgs a) {
   const MeshDims md = dims_of(mp);
-  relax_block<DIM, N>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB, blockIdx.x, 0);
+  relax_block<DIM, N, NET>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB, blockIdx.x, 0);
 }
 
 // Batched form over (simulation, first element) items; partial per item.
@@ -344,7 +443,9 @@ __global__ void __launch_bounds__(256)
     a.guess = a0.guess ? a0.guess + P.elem_base : nullptr;
     a.gamma_k = a0.gamma_k + P.elem_base;
     a.iters = a0.iters ? a0.iters + P.elem_base : nullptr;
-    relax_block<DIM, N>(mp, P.md, a, w.y, it, P.elem_base);
+    a.feats = a0.feats ? a0.feats + P.elem_base * kMlpIn : nullptr;
+    a.vfeat = a0.vfeat ? a0.vfeat + P.elem_base : nullptr;
+    relax_block<DIM, N, false>(mp, P.md, a, w.y, it, P.elem_base);
     __syncthreads();
   }
 }
@@ -375,7 +476,10 @@ template <int DIM, int N>
 static hipError_t relax_one(const MeshParams& mp, const RelaxArgs& a, hipStream_t s) {
   using C = RelaxCfg<DIM, N>;
   const int blocks = (mp.ne + C::EPB - 1) / C::EPB;
-  hipLaunchKernelGGL((relax_kernel<DIM, N>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
+  if (a.model || a.feats)
+    hipLaunchKernelGGL((relax_kernel<DIM, N, true>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
+  else
+    hipLaunchKernelGGL((relax_kernel<DIM, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
   return hipGetLastError();
 }
 
@@ -501,10 +605,16 @@ __global__ void __launch_bounds__(256) apply_kernel(double* u, const double* du,
       u[i] = u[i] + g * du[i];
   }
   if (blockIdx.x == 0) {
-    double inact = 0.0;
+    double inact = 0.0, isum = 0.0, imax = 0.0;
     if (stats_out) {
-      for (int q = threadIdx.x; q < nparts; q += blockDim.x) inact += parts[q].n_inactive;
+      for (int q = threadIdx.x; q < nparts; q += blockDim.x) {
+        inact += parts[q].n_inactive;
+        isum += parts[q].sum_iters;
+        imax = fmax(imax, (double)parts[q].max_iters);
+      }
       inact = block_sum256(inact, sh);
+      isum = block_sum256(isum, sh);
+      imax = -block_min256(-imax, sh);
     }
     if (threadIdx.x == 0) {
       const double dt = *dt_dev;
@@ -519,6 +629,8 @@ __global__ void __launch_bounds__(256) apply_kernel(double* u, const double* du,
         stats_out[1] = dt;
         stats_out[2] = tn;
         stats_out[3] = inact;
+        stats_out[4] = imax;
+        stats_out[5] = isum;
       }
     }
   }

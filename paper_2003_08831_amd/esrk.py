@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libesrk.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "esrk.h")
 
 FP64, FP32_FLUX = 0, 1
+MLP_TRAINED, MLP_MODEL, MLP_IN = 1281, 1298, 5
 SSPRK33, RK44 = 0, 1
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "EHIP", 3: "ENOMEM", 4: "ENOROOT", 5: "ENONPHYS",
@@ -103,6 +104,19 @@ def load():
     L.esrk_batch_run_graph.restype = st
     L.esrk_batch_sync_status.argtypes = [vp, C.POINTER(C.c_int64)]
     L.esrk_batch_sync_status.restype = st
+    L.esrk_local_relaxation_solve_ml.argtypes = [vp, vp, vp, vp, dp, vp, vp, vp, vp, vp, vp,
+                                                 vp]
+    L.esrk_local_relaxation_solve_ml.restype = st
+    L.esrk_set_step_model.argtypes = [vp, vp, vp]
+    L.esrk_set_step_model.restype = st
+    L.esrk_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp]
+    L.esrk_mlp_forward.restype = st
+    L.esrk_mlp_grad.argtypes = [vp, vp, vp, C.c_int, vp, vp, vp]
+    L.esrk_mlp_grad.restype = st
+    L.esrk_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, vp]
+    L.esrk_mlp_adam.restype = st
+    L.esrk_mlp_prepare.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp, vp, vp]
+    L.esrk_mlp_prepare.restype = st
     _lib = L
     return L
 
@@ -187,6 +201,19 @@ class Context:
             self._h, _ptr(u_old), _ptr(du), _ptr(deta), _ptr(gamma_guess), _ptr(gamma_k),
             _ptr(gamma), _ptr(iters), _stream(stream)), "esrk_local_relaxation_solve")
 
+    def local_relaxation_solve_ml(self, u_old, du, deta, dt, gamma_k, gamma, visc_rate=None,
+                                  model=None, feats=None, iters=None, stream=None):
+        _check(load().esrk_local_relaxation_solve_ml(
+            self._h, _ptr(u_old), _ptr(du), _ptr(deta), float(dt), _ptr(visc_rate),
+            _ptr(model), _ptr(feats), _ptr(gamma_k), _ptr(gamma), _ptr(iters),
+            _stream(stream)), "esrk_local_relaxation_solve_ml")
+
+    def set_step_model(self, model=None, feats_out=None):
+        # the context keeps the raw pointers: hold the tensors while they are set
+        self._step_model_refs = (model, feats_out)
+        _check(load().esrk_set_step_model(self._h, _ptr(model), _ptr(feats_out)),
+               "esrk_set_step_model")
+
     def step(self, u, t, dt=0.0, gamma_k=None, stats=None, stream=None):
         _check(load().esrk_step(self._h, _ptr(u), _ptr(t), float(dt), _ptr(gamma_k),
                                 _ptr(stats), _stream(stream)), "esrk_step")
@@ -245,3 +272,27 @@ class Batch:
         bad = C.c_int64(-1)
         rc = load().esrk_batch_sync_status(self._h, C.byref(bad))
         return rc, bad.value
+
+
+def mlp_forward(model, x_norm, y, stream=None):
+    B = 0 if x_norm is None else x_norm.numel() // MLP_IN
+    _check(load().esrk_mlp_forward(_ptr(model), _ptr(x_norm), B, _ptr(y), _stream(stream)),
+           "esrk_mlp_forward")
+
+
+def mlp_grad(model, x_norm, t_norm, grad, loss=None, stream=None):
+    B = t_norm.numel()
+    _check(load().esrk_mlp_grad(_ptr(model), _ptr(x_norm), _ptr(t_norm), B, _ptr(grad),
+                                _ptr(loss), _stream(stream)), "esrk_mlp_grad")
+
+
+def mlp_adam(model, grad, m, v, step, lr, stream=None):
+    _check(load().esrk_mlp_adam(_ptr(model), _ptr(grad), _ptr(m), _ptr(v), int(step),
+                                float(lr), _stream(stream)), "esrk_mlp_adam")
+
+
+def mlp_prepare(model, raw, x_norm, gamma=None, t_norm=None, fit=False, stream=None):
+    B = raw.numel() // MLP_IN
+    _check(load().esrk_mlp_prepare(_ptr(model), _ptr(raw), _ptr(gamma), B, int(bool(fit)),
+                                   _ptr(x_norm), _ptr(t_norm), _stream(stream)),
+           "esrk_mlp_prepare")

@@ -236,3 +236,27 @@ def uniform_state(ms: MeshSpec, rho=1.0, vel=(0.3, -0.2, 0.1), p=1.0) -> np.ndar
     return conserved(ms.dim, ms.gas_gamma, np.full(shape, rho),
                      [np.full(shape, vel[m]) for m in range(ms.dim)],
                      np.full(shape, p)).reshape(-1).copy()
+
+
+# Network for the first relaxation trial point: 5 -> 32 -> 32 -> 1.  Parameter
+# layout W1[32][5], b1[32], W2[32][32], b2[32], w3[32], b3, then the input
+# normalization scale[5], mean[5], std[5] and the output out_mean, out_std.
+MLP_IN, MLP_H, MLP_TRAINED, MLP_MODEL = 5, 32, 1281, 1298
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Xavier-uniform weights, zero biases, identity normalization (float32)."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(MLP_MODEL, dtype=np.float64)
+
+    def xavier(fan_out, fan_in):
+        a = math.sqrt(6.0 / (fan_in + fan_out))
+        return rng.uniform(-a, a, size=fan_out * fan_in)
+
+    p[0:160] = xavier(MLP_H, MLP_IN)
+    p[192:1216] = xavier(MLP_H, MLP_H)
+    p[1248:1280] = xavier(1, MLP_H)
+    p[1281:1286] = 1.0   # scale
+    p[1291:1296] = 1.0   # std
+    p[1297] = 1.0        # out_std
+    return p.astype(np.float32)

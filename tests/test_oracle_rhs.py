@@ -164,3 +164,25 @@ def test_vortex_spatial_convergence(orc):
         errs.append(math.sqrt(((e ** 2) * M).sum() / 100.0))
     rates = [math.log(errs[i] / errs[i + 1], 2) for i in range(2)]
     assert rates[-1] > 3.3, (errs, rates)
+
+
+def test_elem_max_speed_uniform_and_single_node(orc):
+    """A uniform state has sum_m |v_m| + dim c in every element; raising the
+    velocity at one node changes only its element's value."""
+    import math as _m
+    ms = I.tgv_mesh(nel=2, deg=2)
+    u = I.uniform_state(ms, rho=1.3, vel=(0.3, -0.2, 0.1), p=0.9)
+    m = orc_mesh(orc, ms)
+    s = orc.elem_max_speed(m, u)
+    c = _m.sqrt(1.4 * 0.9 / 1.3)
+    np.testing.assert_allclose(s, 0.6 + 3 * c, rtol=1e-15)
+    uv = view(ms, u).copy()
+    k, i = 5, 7
+    uv[1, k, i] *= 3.0  # rho v_1 tripled, energy kept: pressure drops
+    rho, E = uv[0, k, i], uv[4, k, i]
+    v = np.array([uv[1, k, i], uv[2, k, i], uv[3, k, i]]) / rho
+    p = 0.4 * (E - 0.5 * rho * np.dot(v, v))
+    s2 = orc.elem_max_speed(m, uv.reshape(-1))
+    expect = np.abs(v).sum() + 3 * _m.sqrt(1.4 * p / rho)
+    assert abs(s2[k] - max(expect, 0.6 + 3 * c)) <= 1e-15 * expect
+    assert np.all(np.delete(s2, k) == s[0])
