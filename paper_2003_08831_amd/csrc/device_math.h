@@ -19,10 +19,21 @@ template <> struct LnSeries<float> {
   static constexpr int terms = 4;
 };
 
+// Short series used when every lane of the wave has f^2 < kLnShortCut (smooth
+// flow): 3 terms in double (first dropped term u^3/7 < 1.5e-19), 2 in float
+// (u^2/5 < 2e-13).
+constexpr double kLnShortCut = 1e-6;
+template <typename T> struct LnShort;
+template <> struct LnShort<double> {
+  static constexpr int terms = 3;
+};
+template <> struct LnShort<float> {
+  static constexpr int terms = 2;
+};
+
 // F(u) = atanh(f)/f = sum_k u^k / (2k+1),   u = f^2
-template <typename T>
+template <typename T, int K = LnSeries<T>::terms>
 __device__ __forceinline__ T atanh_over(T u) {
-  constexpr int K = LnSeries<T>::terms;
   T s = T(1) / T(2 * K - 1);
 #pragma unroll
   for (int k = K - 2; k >= 0; --k) s = s * u + T(1) / T(2 * k + 1);
@@ -31,7 +42,7 @@ __device__ __forceinline__ T atanh_over(T u) {
 
 // G(u) = f/atanh(f) = 1/F(u), series in u with rational coefficients
 // g_0 = 1, g_k = -sum_{j<k} g_j / (2(k-j)+1).
-template <typename T>
+template <typename T, int K = LnSeries<T>::terms>
 __device__ __forceinline__ T inv_atanh_over(T u) {
   constexpr double g[8] = {1.0,
                            -1.0 / 3.0,
@@ -41,7 +52,6 @@ __device__ __forceinline__ T inv_atanh_over(T u) {
                            -10196.0 / 467775.0,
                            -10719068.0 / 638512875.0,
                            -25865068.0 / 1915538625.0};
-  constexpr int K = LnSeries<T>::terms;
   T s = T(g[K - 1]);
 #pragma unroll
   for (int k = K - 2; k >= 0; --k) s = s * u + T(g[k]);
@@ -72,16 +82,26 @@ template <typename T>
 struct PairMeans {
   T rho_ln, inv_beta_ln, p_hat;
 };
-template <typename T>
+// WAVE_UNIFORM: the series length may be chosen per wave (volume pairs, each
+// evaluated once).  Interface fluxes are evaluated by both elements of a face
+// and must not depend on other lanes: they use the per-pair rule only.
+template <typename T, bool WAVE_UNIFORM = false>
 __device__ __forceinline__ PairMeans<T> pair_means(T ra, T rb, T ba, T bb) {
   const T sr = ra + rb, dr = ra - rb;
   const T sb = ba + bb, db = ba - bb;
-  const T rsr = rcp(sr), rsb = rcp(sb);
+  // one reciprocal for both sums
+  const T rp = rcp(sr * sb);
+  const T rsr = sb * rp, rsb = sr * rp;
   const T fr = dr * rsr, fb = db * rsb;
   const T ur = fr * fr, ub = fb * fb;
   PairMeans<T> m;
   m.p_hat = T(0.5) * sr * rsb;
-  if (ur < T(kLnCut) && ub < T(kLnCut)) {
+  // wave-uniform choice of the series length (one ballot, no divergence)
+  if (WAVE_UNIFORM && __all(ur < T(kLnShortCut) && ub < T(kLnShortCut))) {
+    constexpr int K = LnShort<T>::terms;
+    m.rho_ln = T(0.5) * sr * inv_atanh_over<T, K>(ur);
+    m.inv_beta_ln = T(2) * rsb * atanh_over<T, K>(ub);
+  } else if (ur < T(kLnCut) && ub < T(kLnCut)) {
     m.rho_ln = T(0.5) * sr * inv_atanh_over(ur);
     m.inv_beta_ln = T(2) * rsb * atanh_over(ub);
   } else {

@@ -16,10 +16,92 @@
 //                 the face neighbours in registers, Visc -> visc buffer (FP64) and
 //                 the element's viscous entropy dissipation.
 // The fused stage kernel adds the visc buffer to the inviscid right-hand side.
+#include <type_traits>
+
 #include "device_math.h"
 #include "internal.h"
 
+// 1: in FP32 mode the derivative applies D (.) along each direction run on the
+// matrix cores (v_mfma_f32_4x4x1f32, 16 blocks); 0: VALU loops as in FP64.
+#ifndef ESRK_NS_MFMA
+#define ESRK_NS_MFMA 1
+#endif
+
 namespace esrk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Derivative applies of one block on the matrix cores (FP32):
+//   out[(d NV + v) E ND + e ND + node(d, l, i)]
+//       = sum_j D[i][j] in[d * in_dstride + v E ND + e ND + node(d, l, j)]
+// for every direction d, field v, element e of the block and line l along d.
+// Rows r = ((d NV + v) E + e) NL + l are the GEMM's M dimension, the node j
+// along the line its K dimension (one MFMA per j) and the output node i its N
+// dimension (groups of 4).  v_mfma_f32_4x4x1f32 with 16 blocks: lane 4b + t
+// supplies A = row 64 g + 4b + t and B = D[4 c0 + t][j]; it receives rows
+// 64 g + 4b + (0..3) of output column 4 c0 + t.  Every lane of a wave takes
+// part (out-of-range rows and columns are zero-padded).
+template <int DIM, int N, int E, int NV>
+__device__ __forceinline__ void dapply_mfma(const float* in, int in_dstride, float* out,
+                                            const double* D2, int nthreads) {
+  constexpr int ND = (DIM == 1) ? N : (DIM == 2) ? N * N : N * N * N;
+  constexpr int NL = ND / N;
+  constexpr int R = DIM * NV * E * NL;
+  constexpr int G = (R + 63) / 64;
+  constexpr int CG = (N + 3) / 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = nthreads >> 6;
+  const int t = lane & 3;
+  float B[CG][N];
+#pragma unroll
+  for (int c = 0; c < CG; ++c)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int i = 4 * c + t;
+      B[c][j] = i < N ? float(0.5 * D2[i * N + j]) : 0.f;
+    }
+  for (int g = wave; g < G; g += nw) {
+    // this lane's A row
+    const int row = 64 * g + lane;
+    float x[N];
+    {
+      const bool ok = row < R;
+      const int rr = ok ? row : 0;
+      const int l = rr % NL;
+      const int ev = rr / NL;  // (d NV + v) E + e
+      const int e = ev % E;
+      const int dv = ev / E;
+      const int d = dv / NV, v = dv - d * NV;
+      const int stride = (d == 0) ? 1 : (d == 1) ? N : N * N;
+      const int base = (l % stride) + (l / stride) * stride * N;
+      const float* src = in + d * in_dstride + (v * E + e) * ND + base;
+#pragma unroll
+      for (int j = 0; j < N; ++j) x[j] = ok ? src[j * stride] : 0.f;
+    }
+#pragma unroll
+    for (int c = 0; c < CG; ++c) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(x[j], B[c][j], acc, 0, 0, 0);
+      const int i = 4 * c + t;
+      if (i < N) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int ro = 64 * g + (lane & ~3) + q;
+          if (ro < R) {
+            const int l = ro % NL;
+            const int ev = ro / NL;
+            const int d = (ev / E) / NV;
+            const int stride = (d == 0) ? 1 : (d == 1) ? N : N * N;
+            const int base = (l % stride) + (l / stride) * stride * N;
+            out[ev * ND + base + i * stride] = acc[q];
+          }
+        }
+      }
+    }
+  }
+}
 
 template <int DIM, int N>
 struct NsGeo {
@@ -30,6 +112,9 @@ struct NsGeo {
   static constexpr int RAW = E * ND;
   static constexpr int THREADS = ((RAW + 63) / 64) * 64;
 };
+
+template <typename T>
+constexpr bool kUseMfma = ESRK_NS_MFMA && std::is_same<T, float>::value;
 
 template <int DIM>
 __device__ __forceinline__ int ns_neighbour(const MeshParams& mp, int k, int m, int dir) {
@@ -173,6 +258,21 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
     }
   }
   __syncthreads();
+  if constexpr (kUseMfma<T>) {
+    __shared__ float sout[DIM * NV * E * ND];
+    dapply_mfma<DIM, N, E, NV>(sw, 0, sout, mp.D2, G::THREADS);
+    __syncthreads();
+    if (!valid) return;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const T metric = T(mp.two_over_h[d]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        theta[((long long)d * NV + v) * Ntot + (long long)k * ND + i] =
+            metric * (sout[(d * NV + v) * E * ND + e * ND + i] + lift[d][v]);
+    }
+    return;
+  }
   if (!valid) return;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -277,7 +377,23 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
     }
   }
   __syncthreads();
-  if (valid) {
+  if constexpr (kUseMfma<T>) {
+    __shared__ float sout[DIM * NV * E * ND];
+    dapply_mfma<DIM, N, E, NV>(sg, NV * E * ND, sout, mp.D2, G::THREADS);
+    __syncthreads();
+    if (valid) {
+      const long long gi = (long long)k * ND + i;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+          acc += mp.two_over_h[d] *
+                 double(sout[(d * NV + v) * E * ND + e * ND + i] + lift[d][v]);
+        visc[v * Ntot + gi] = acc;
+      }
+    }
+  } else if (valid) {
     const long long gi = (long long)k * ND + i;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

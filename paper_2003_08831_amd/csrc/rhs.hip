@@ -242,7 +242,8 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
     for (int p0 = 0; p0 < N; ++p0) {
 #pragma unroll
       for (int p1 = p0 + 1; p1 < N; ++p1) {
-        const PairMeans<T> mn = pair_means(P[p0].rho, P[p1].rho, P[p0].beta, P[p1].beta);
+        const PairMeans<T> mn =
+            pair_means<T, true>(P[p0].rho, P[p1].rho, P[p0].beta, P[p1].beta);
         T F[NV];
         ec_flux_from_means<T, DIM>(m, P[p0], P[p1], mn, half_inv_gm1, F);
         const T d01 = T(mp.D2[p0 * N + p1]), d10 = T(mp.D2[p1 * N + p0]);
@@ -297,6 +298,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
 
   // ---- phase 2: node epilogue ----
   const double ggd = mp.gg;
+  const double inv_gm1d = 1.0 / (ggd - 1.0);
   double dt = 0.0;
   if (a.stage_mode) {
     dt = a.speed_parts ? *s_dt : (a.dt_dev ? *a.dt_dev : a.dt_host);
@@ -353,7 +355,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
     }
     const double lnr = log(rho), lnb = log(beta);
     const double s_phys = (1.0 - ggd) * lnr - 0.6931471805599453 - lnb;  // ln p - g ln rho
-    double wdot = ((ggd - s_phys) / (ggd - 1.0) - beta * v2) * kv[0];
+    double wdot = ((ggd - s_phys) * inv_gm1d - beta * v2) * kv[0];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) wdot += 2.0 * beta * vel[d] * kv[1 + d];
     wdot += -2.0 * beta * kv[NV - 1];
