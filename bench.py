@@ -50,7 +50,122 @@ def parse():
     p.add_argument("--kernel-reps", type=int, default=50)
     p.add_argument("--copy-calib", action="store_true",
                    help="run one 256 MiB device-to-device copy first (counter calibration)")
+    p.add_argument("--no-variants", action="store_true",
+                   help="skip the Navier-Stokes, batched and learned-guess measurements")
     return p.parse_args()
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def ns_variant(esrk, I, torch, precision, steps, warmup, nel=32, deg=4):
+    """3-D Navier-Stokes TGV (Re 1600, Pr 0.72, Mach 0.1), whole locally relaxed
+    RK(4,4) steps; FP32 mode runs the viscous derivative applies on MFMA."""
+    ms = I.tgv_mesh(nel, deg, mu=1.0 / 1600.0)
+    cfg = esrk.make_config(ms.dim, ms.deg, ms.nel, ms.lo, ms.hi, gas_gamma=ms.gas_gamma,
+                           mu=ms.mu, prandtl=ms.prandtl, precision=precision,
+                           tableau=esrk.RK44, cfl=0.5)
+    ctx = esrk.Context(cfg)
+    u = torch.as_tensor(I.tgv_state(ms, MACH)).to("cuda")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        ctx.step(u, t)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(steps):
+        ctx.step(u, t)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    rc, bad = ctx.sync_status()
+    if rc != 0:
+        raise RuntimeError(f"NS variant: device status {esrk.STATUS.get(rc)} at element {bad}")
+    N = ctx.N
+    del ctx, u
+    torch.cuda.empty_cache()
+    return {"value": round(N * 4 * steps / (ms_total * 1e-3), 1),
+            "ms_per_step": round(ms_total / steps, 4), "nodes": N, "steps": steps}
+
+
+def batch_variant(esrk, I, torch, steps, nsims=256):
+    """256 independent 2-D Euler Kelvin-Helmholtz runs of uneven size (16^2 to
+    64^2 elements, p = 3, seeded), FP32 flux, SSPRK(3,3); one kernel per stage
+    over all simulations, autotuned tile, steps replayed from a hipGraph."""
+    specs = I.kh_batch_specs(nsims, seed=0)
+    cfgs, states = [], []
+    for nel, amp, k in specs:
+        ms = I.kh_mesh(nel, 3)
+        cfgs.append(esrk.make_config(2, 3, ms.nel, ms.lo, ms.hi, precision=esrk.FP32_FLUX,
+                                     tableau=esrk.SSPRK33, cfl=0.5))
+        states.append(I.kh_state(ms, amp, k))
+    b = esrk.Batch(cfgs)
+    u = torch.zeros(b.len, dtype=torch.float64, device="cuda")
+    for s, st in enumerate(states):
+        u[b.offsets[s]:b.offsets[s] + st.size] = torch.as_tensor(st, device="cuda")
+    t = torch.zeros(b.nsims, dtype=torch.float64, device="cuda")
+    g = torch.zeros(b.nsims, dtype=torch.float64, device="cuda")
+    tile = b.autotune(u)
+    b.step(u, t, g)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        b.run_graph(u, t, steps, g, stream=stream)  # capture + first replay
+    stream.synchronize()
+    e0, e1 = _events(torch)
+    e0.record(stream)
+    with torch.cuda.stream(stream):
+        b.run_graph(u, t, steps, g, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1)
+    e0.record()
+    for _ in range(steps):
+        b.step(u, t, g)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_eager = e0.elapsed_time(e1)
+    rc, bad = b.sync_status()
+    if rc != 0:
+        raise RuntimeError(f"batch variant: device status {esrk.STATUS.get(rc)} at {bad}")
+    N = b.len // 4
+    del b, u
+    torch.cuda.empty_cache()
+    return {"value": round(N * 3 * steps / (ms_graph * 1e-3), 1),
+            "ms_per_step": round(ms_graph / steps, 4),
+            "eager_ms_per_step": round(ms_eager / steps, 4), "nodes": N, "sims": nsims,
+            "tile": tile, "steps": steps}
+
+
+def mlp_variant(esrk, I, torch, learn, gain_steps=4):
+    """Learned first trial point of the relaxation solve on the Navier-Stokes
+    TGV (32^3, p = 4): trained on samples logged from Euler TGV (16^3, p = 3)
+    and Navier-Stokes TGV steps, then plain / previous-step / network first
+    trial points compared on the same increments."""
+    runs = []
+    ms = I.tgv_mesh(NEL, DEG)
+    ctx = esrk.Context(esrk.make_config(3, DEG, ms.nel, ms.lo, ms.hi, tableau=esrk.RK44))
+    u = torch.as_tensor(I.tgv_state(ms, MACH)).to("cuda")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    runs.append(learn.collect(ctx, u, t, 20))
+    del ctx, u
+    ms = I.tgv_mesh(32, 4, mu=1.0 / 1600.0)
+    cfg = esrk.make_config(3, 4, ms.nel, ms.lo, ms.hi, mu=ms.mu, prandtl=ms.prandtl,
+                           tableau=esrk.RK44)
+    ctx = esrk.Context(cfg)
+    u = torch.as_tensor(I.tgv_state(ms, MACH)).to("cuda")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    runs.append(learn.collect(ctx, u, t, 8))
+    model, hist = learn.train(runs, steps=1500, batch=4096, lr=1e-3)
+    res = learn.gain(ctx, u, t, gain_steps, model)
+    del ctx, u
+    torch.cuda.empty_cache()
+    return {"samples": hist["n_train"] + hist["n_val"], "train_mse": round(hist["train_final"], 4),
+            "val_mse": None if hist["val_final"] is None else round(hist["val_final"], 4),
+            "phi_evals_per_elem": {k: round(v["evals"], 3) for k, v in res.items()},
+            "relax_ms": {k: round(v["ms"], 4) for k, v in res.items()},
+            "max_gamma_diff_vs_plain": {k: v["dgamma"] for k, v in res.items()}}
 
 
 def run_mode(esrk, I, torch, precision, steps, warmup):
@@ -189,6 +304,14 @@ def main():
         "run": {"gamma_last": r64["gamma"], "dt_last": r64["dt"], "t_end": r64["t"]},
         "roofline": roof,
     }
+    if not a.no_variants:
+        from paper_2003_08831_amd import learn
+        out["variants"] = {
+            "ns_tgv_32cubed_p4_fp64": ns_variant(esrk, I, torch, esrk.FP64, 10, 2),
+            "ns_tgv_32cubed_p4_fp32_mfma": ns_variant(esrk, I, torch, esrk.FP32_FLUX, 10, 2),
+            "kh_batch_256_fp32_graph": batch_variant(esrk, I, torch, 20),
+            "learned_guess_ns_tgv": mlp_variant(esrk, I, torch, learn),
+        }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(I, a.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -118,7 +118,12 @@ esrk_status esrk_rk_stage(esrk_ctx* ctx, int stage, double dt, const double* u_o
  * eta_k(u_old) for Runge-Kutta), gamma_k is the positive root of
  *   phi_k(g) = (eta_k(u_old + g du) - eta_k(u_old) - g deta_k) / g,
  * solved per element to root_tol; elements whose root is not determinable in
- * FP64 (no curvature above round-off) get +INF.  *gamma (device scalar) =
+ * FP64 (curvature r_k(1) - phi_k(0) at most
+ * 64 eps (sum_i M_i sum_v |w_v du_v| + |deta_k|)) get +INF.  With precision
+ * ESRK_FP32_FLUX the increments carry FP32 flux rounding: eps is then the
+ * FP32 epsilon, and an element with phi_k(0) >= 0 whose entropy change r_k(1)
+ * stays within that level is inactive too.  Any other element with
+ * phi_k(0) >= 0 latches ESRK_ENOROOT.  *gamma (device scalar) =
  * min_k gamma_k, or 1 if every element is inactive.  gamma_guess (nullable,
  * float [num_elems]) seeds the solve: after phi_k(1) it is the next trial
  * point if it lies in (0, gamma_max]; the result does not depend on it beyond
@@ -235,10 +240,14 @@ esrk_status esrk_mlp_prepare(float* model, const float* raw, const double* gamma
 /* Network on normalized inputs: y[b] = net(x_norm[b][0..5)), B samples. */
 esrk_status esrk_mlp_forward(const float* model, const float* x_norm, int B, float* y,
                              void* stream);
+/* Device workspace (number of floats) that esrk_mlp_grad needs for B samples. */
+size_t esrk_mlp_grad_work_size(int B);
 /* grad[ESRK_MLP_TRAINED] of L = (1/B) sum_b (net(x_b) - t_b)^2 and L (loss,
- * nullable, device scalar); one workgroup, deterministic summation order. */
+ * nullable, device scalar).  work: device buffer of esrk_mlp_grad_work_size(B)
+ * floats (per-block partial gradients, summed in block order afterwards, so
+ * the result is deterministic). */
 esrk_status esrk_mlp_grad(const float* model, const float* x_norm, const float* t_norm, int B,
-                          float* grad, float* loss, void* stream);
+                          float* grad, float* loss, float* work, void* stream);
 /* One Adam update (beta1 0.9, beta2 0.999, eps 1e-8) of the trained
  * parameters; m, v: device moment vectors (zero before step 1). */
 esrk_status esrk_mlp_adam(float* model, const float* grad, float* m, float* v, int step,

@@ -283,6 +283,7 @@ static esrk::RelaxArgs relax_args(esrk_ctx* x, const double* u_old, const double
   r.tol = x->cfg.root_tol;
   r.gamma_max = x->cfg.gamma_max;
   r.maxit = x->cfg.root_maxit;
+  r.fp32_increments = x->cfg.precision == ESRK_FP32_FLUX;
   return r;
 }
 
@@ -388,10 +389,15 @@ esrk_status esrk_mlp_forward(const float* model, const float* x_norm, int B, flo
   return hip_status(esrk::launch_mlp_forward(model, x_norm, B, y, (hipStream_t)stream));
 }
 
+size_t esrk_mlp_grad_work_size(int B) {
+  if (B < 1) return 0;
+  return (size_t)esrk::mlp_grad_blocks(B) * (size_t)(ESRK_MLP_TRAINED + 1);
+}
+
 esrk_status esrk_mlp_grad(const float* model, const float* x_norm, const float* t_norm, int B,
-                          float* grad, float* loss, void* stream) {
-  if (!model || !x_norm || !t_norm || B < 1 || !grad) return ESRK_EINVAL;
-  return hip_status(esrk::launch_mlp_grad(model, x_norm, t_norm, B, grad, loss,
+                          float* grad, float* loss, float* work, void* stream) {
+  if (!model || !x_norm || !t_norm || B < 1 || !grad || !work) return ESRK_EINVAL;
+  return hip_status(esrk::launch_mlp_grad(model, x_norm, t_norm, B, grad, loss, work,
                                           (hipStream_t)stream));
 }
 

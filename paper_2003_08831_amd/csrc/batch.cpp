@@ -117,7 +117,7 @@ hipError_t enqueue_step(esrk_batch* b, double* u, double* t, double* gamma, int 
     yin = bufs[i & 1];
   }
   if (e == hipSuccess) {
-    esrk::RelaxArgs r;
+    esrk::RelaxArgs r{};
     r.u_old = u;
     r.du = b->du;
     r.deta = b->deta;
@@ -129,6 +129,7 @@ hipError_t enqueue_step(esrk_batch* b, double* u, double* t, double* gamma, int 
     r.tol = b->cfg0.root_tol;
     r.gamma_max = b->cfg0.gamma_max;
     r.maxit = b->cfg0.root_maxit;
+    r.fp32_increments = b->cfg0.precision == ESRK_FP32_FLUX;
     e = esrk::launch_relax_batch(b->mp, r, b->sims, b->relax_items, b->n_relax_items,
                                  grid_for(b->n_relax_items), s);
   }

@@ -143,6 +143,9 @@ struct RelaxArgs {
   DevScalars* scal;
   double tol, gamma_max;
   int maxit;
+  // FP32-flux increments: an element whose phi(0) >= 0 while its entropy
+  // change r(1) stays within the FP32 rounding level is inactive, not ENOROOT
+  int fp32_increments;
 };
 int relax_blocks(const MeshParams& mp);
 hipError_t launch_relax(const MeshParams& mp, const RelaxArgs& a, hipStream_t s);
@@ -161,8 +164,10 @@ hipError_t launch_apply(const MeshParams& mp, double* u, const double* du, doubl
 hipError_t launch_mlp_forward(const float* p, const float* X, int B, float* Y, hipStream_t s);
 hipError_t launch_mlp_prepare(float* p, const float* raw, const double* gamma, int B, int fit,
                               float* xn, float* tn, hipStream_t s);
+int mlp_grad_blocks(int B);
+// part: mlp_grad_blocks(B) * (kMlpTrained + 1) floats of workspace
 hipError_t launch_mlp_grad(const float* p, const float* X, const float* T, int B, float* grad,
-                           float* loss, hipStream_t s);
+                           float* loss, float* part, hipStream_t s);
 hipError_t launch_mlp_adam(float* p, const float* g, float* m, float* v, int step, float lr,
                            hipStream_t s);
 

@@ -12,8 +12,8 @@
 //   gamma_guess = 1 + dt^2 (out_mean + out_std y).
 //
 // Kernels: inference (thread per sample), gradient of the mean squared error
-// (one 1024-thread block, samples in chunks of 64 staged in LDS, every
-// parameter's gradient summed over the samples in a fixed order) and Adam.
+// (blocks of 64 samples staged in LDS write partial gradients, a second kernel
+// sums them in block order: deterministic), Adam, and the sample normalization.
 #include "internal.h"
 
 namespace esrk {
@@ -43,97 +43,108 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const float* __restric
   Y[b] = y;
 }
 
-constexpr int kChunk = 64;
+constexpr int kChunk = 64;    // samples per gradient block
+constexpr int kGradThreads = 256;
 
-__global__ void __launch_bounds__(1024) mlp_grad_kernel(const float* __restrict__ p,
-                                                        const float* __restrict__ X,
-                                                        const float* __restrict__ T, int B,
-                                                        float* __restrict__ grad,
-                                                        float* __restrict__ loss) {
+// Gradient of the mean squared error, stage 1: block c takes samples
+// [64 c, 64 c + 64), runs forward and backward with one thread per sample and
+// writes its partial gradient (and partial loss) to part[c][0..1282).
+__global__ void __launch_bounds__(kGradThreads) mlp_grad_part_kernel(
+    const float* __restrict__ p, const float* __restrict__ X, const float* __restrict__ T,
+    int B, float* __restrict__ part) {
   __shared__ float sx[kChunk][kMlpIn];
-  __shared__ float sh1[kChunk][kMlpH], sh2[kChunk][kMlpH];
-  __shared__ float sz1[kChunk][kMlpH], sz2[kChunk][kMlpH];
+  __shared__ float sh1[kChunk][kMlpH + 1], sh2[kChunk][kMlpH + 1];
+  __shared__ float sz1[kChunk][kMlpH + 1], sz2[kChunk][kMlpH + 1];
   __shared__ float sdy[kChunk], sres[kChunk];
   const int tid = threadIdx.x;
-  // each thread owns parameters q = tid and q = tid + 1024 (if < 1281)
-  float g0 = 0.f, g1 = 0.f, L = 0.f;
-  for (int c0 = 0; c0 < B; c0 += kChunk) {
-    const int nb = min(kChunk, B - c0);
-    if (tid < nb) {
-      const int b = c0 + tid;
-      float x[kMlpIn];
+  const int c0 = blockIdx.x * kChunk;
+  const int nb = min(kChunk, B - c0);
+  if (tid < nb) {
+    const int b = c0 + tid;
+    float x[kMlpIn];
 #pragma unroll
-      for (int i = 0; i < kMlpIn; ++i) {
-        x[i] = X[b * kMlpIn + i];
-        sx[tid][i] = x[i];
-      }
-      float h1[kMlpH], h2[kMlpH];
-#pragma unroll
-      for (int j = 0; j < kMlpH; ++j) {
-        float s = p[kOffB1 + j];
-#pragma unroll
-        for (int i = 0; i < kMlpIn; ++i) s += p[kOffW1 + j * kMlpIn + i] * x[i];
-        h1[j] = tanhf(s);
-        sh1[tid][j] = h1[j];
-      }
-      float y = p[kOffB3];
-      for (int j = 0; j < kMlpH; ++j) {
-        float s = p[kOffB2 + j];
-#pragma unroll
-        for (int i = 0; i < kMlpH; ++i) s += p[kOffW2 + j * kMlpH + i] * h1[i];
-        h2[j] = tanhf(s);
-        sh2[tid][j] = h2[j];
-        y += p[kOffW3 + j] * h2[j];
-      }
-      const float r = y - T[b];
-      sres[tid] = r * r;
-      const float dy = 2.f * r / float(B);
-      sdy[tid] = dy;
-      float z2[kMlpH];
-#pragma unroll
-      for (int j = 0; j < kMlpH; ++j) {
-        z2[j] = dy * p[kOffW3 + j] * (1.f - h2[j] * h2[j]);
-        sz2[tid][j] = z2[j];
-      }
-      for (int i = 0; i < kMlpH; ++i) {
-        float s = 0.f;
-#pragma unroll
-        for (int j = 0; j < kMlpH; ++j) s += p[kOffW2 + j * kMlpH + i] * z2[j];
-        sz1[tid][i] = s * (1.f - h1[i] * h1[i]);
-      }
+    for (int i = 0; i < kMlpIn; ++i) {
+      x[i] = X[b * kMlpIn + i];
+      sx[tid][i] = x[i];
     }
-    __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-      const int q = tid + pass * 1024;
-      if (q >= kMlpTrained) break;
-      float acc = 0.f;
-      if (q < kOffB1) {
-        const int j = q / kMlpIn, i = q - j * kMlpIn;
-        for (int b = 0; b < nb; ++b) acc += sz1[b][j] * sx[b][i];
-      } else if (q < kOffW2) {
-        const int j = q - kOffB1;
-        for (int b = 0; b < nb; ++b) acc += sz1[b][j];
-      } else if (q < kOffB2) {
-        const int j = (q - kOffW2) / kMlpH, i = (q - kOffW2) - j * kMlpH;
-        for (int b = 0; b < nb; ++b) acc += sz2[b][j] * sh1[b][i];
-      } else if (q < kOffW3) {
-        const int j = q - kOffB2;
-        for (int b = 0; b < nb; ++b) acc += sz2[b][j];
-      } else if (q < kOffB3) {
-        const int j = q - kOffW3;
-        for (int b = 0; b < nb; ++b) acc += sdy[b] * sh2[b][j];
-      } else {
-        for (int b = 0; b < nb; ++b) acc += sdy[b];
-      }
-      if (pass == 0) g0 += acc; else g1 += acc;
+    float h1[kMlpH], h2[kMlpH];
+#pragma unroll
+    for (int j = 0; j < kMlpH; ++j) {
+      float s = p[kOffB1 + j];
+#pragma unroll
+      for (int i = 0; i < kMlpIn; ++i) s += p[kOffW1 + j * kMlpIn + i] * x[i];
+      h1[j] = tanhf(s);
+      sh1[tid][j] = h1[j];
     }
-    if (tid == 0)
-      for (int b = 0; b < nb; ++b) L += sres[b];
-    __syncthreads();
+    float y = p[kOffB3];
+    for (int j = 0; j < kMlpH; ++j) {
+      float s = p[kOffB2 + j];
+#pragma unroll
+      for (int i = 0; i < kMlpH; ++i) s += p[kOffW2 + j * kMlpH + i] * h1[i];
+      h2[j] = tanhf(s);
+      sh2[tid][j] = h2[j];
+      y += p[kOffW3 + j] * h2[j];
+    }
+    const float r = y - T[b];
+    sres[tid] = r * r;
+    const float dy = 2.f * r / float(B);
+    sdy[tid] = dy;
+    float z2[kMlpH];
+#pragma unroll
+    for (int j = 0; j < kMlpH; ++j) {
+      z2[j] = dy * p[kOffW3 + j] * (1.f - h2[j] * h2[j]);
+      sz2[tid][j] = z2[j];
+    }
+    for (int i = 0; i < kMlpH; ++i) {
+      float s = 0.f;
+#pragma unroll
+      for (int j = 0; j < kMlpH; ++j) s += p[kOffW2 + j * kMlpH + i] * z2[j];
+      sz1[tid][i] = s * (1.f - h1[i] * h1[i]);
+    }
   }
-  grad[tid] = g0;
-  if (tid + 1024 < kMlpTrained) grad[tid + 1024] = g1;
-  if (tid == 0 && loss) *loss = L / float(B);
+  __syncthreads();
+  float* out = part + (long long)blockIdx.x * (kMlpTrained + 1);
+  for (int q = tid; q < kMlpTrained; q += kGradThreads) {
+    float acc = 0.f;
+    if (q < kOffB1) {
+      const int j = q / kMlpIn, i = q - j * kMlpIn;
+      for (int b = 0; b < nb; ++b) acc += sz1[b][j] * sx[b][i];
+    } else if (q < kOffW2) {
+      const int j = q - kOffB1;
+      for (int b = 0; b < nb; ++b) acc += sz1[b][j];
+    } else if (q < kOffB2) {
+      const int j = (q - kOffW2) / kMlpH, i = (q - kOffW2) - j * kMlpH;
+      for (int b = 0; b < nb; ++b) acc += sz2[b][j] * sh1[b][i];
+    } else if (q < kOffW3) {
+      const int j = q - kOffB2;
+      for (int b = 0; b < nb; ++b) acc += sz2[b][j];
+    } else if (q < kOffB3) {
+      const int j = q - kOffW3;
+      for (int b = 0; b < nb; ++b) acc += sdy[b] * sh2[b][j];
+    } else {
+      for (int b = 0; b < nb; ++b) acc += sdy[b];
+    }
+    out[q] = acc;
+  }
+  if (tid == 0) {
+    float L = 0.f;
+    for (int b = 0; b < nb; ++b) L += sres[b];
+    out[kMlpTrained] = L;
+  }
+}
+
+// Stage 2: grad[q] = sum over blocks (in block order) of the partials; the
+// last entry of each partial row is the block's squared-residual sum.
+__global__ void __launch_bounds__(256) mlp_grad_reduce_kernel(const float* __restrict__ part,
+                                                              int nblk, int B,
+                                                              float* __restrict__ grad,
+                                                              float* __restrict__ loss) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q > kMlpTrained) return;
+  float s = 0.f;
+  for (int c = 0; c < nblk; ++c) s += part[(long long)c * (kMlpTrained + 1) + q];
+  if (q < kMlpTrained) grad[q] = s;
+  else if (loss) *loss = s / float(B);
 }
 
 __global__ void __launch_bounds__(256) mlp_adam_kernel(float* __restrict__ p,
@@ -254,9 +265,17 @@ hipError_t launch_mlp_forward(const float* p, const float* X, int B, float* Y, h
   return hipGetLastError();
 }
 
+int mlp_grad_blocks(int B) { return (B + kChunk - 1) / kChunk; }
+
 hipError_t launch_mlp_grad(const float* p, const float* X, const float* T, int B, float* grad,
-                           float* loss, hipStream_t s) {
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3(1), dim3(1024), 0, s, p, X, T, B, grad, loss);
+                           float* loss, float* part, hipStream_t s) {
+  const int nblk = mlp_grad_blocks(B);
+  hipLaunchKernelGGL(mlp_grad_part_kernel, dim3(nblk), dim3(kGradThreads), 0, s, p, X, T, B,
+                     part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mlp_grad_reduce_kernel, dim3((kMlpTrained + 1 + 255) / 256), dim3(256), 0,
+                     s, part, nblk, B, grad, loss);
   return hipGetLastError();
 }
 

@@ -243,7 +243,12 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
   if (want_feats) smax = seg_max<G>(smax);
   const double deta = valid ? a.deta[k] : 0.0;
   const double phi0 = A - deta;
-  const double noise = 64.0 * DBL_EPSILON * (scale + fabs(deta));
+  // round-off level of the element's entropy increments: FP64 increments, or
+  // increments built from FP32 flux differences (then the estimate and the
+  // update of an element that barely changes are FP32 noise and its root is
+  // not determined)
+  const double noise_eps = a.fp32_increments ? (double)FLT_EPSILON : DBL_EPSILON;
+  const double noise = 64.0 * noise_eps * (scale + fabs(deta));
 
   // relative entropy sum B(g) and admissibility along the line
   // (an inadmissible node makes the element sum +INF)
@@ -330,6 +335,13 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
         continue;
       }
       if (!(phi0 < 0.0)) {
+        // with FP32-flux increments the estimate carries FP32 rounding: an
+        // entropy change r(1) within that level leaves gamma undetermined
+        if (a.fp32_increments && ok && phi0 + q <= noise) {
+          gk = INFINITY;
+          done = true;
+          continue;
+        }
         gk = 0.0;
         done = true;
         if (sl == 0) latch_r(a.scal, ESRK_ENOROOT, elem_base + k);

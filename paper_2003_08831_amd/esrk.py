@@ -111,8 +111,10 @@ def load():
     L.esrk_set_step_model.restype = st
     L.esrk_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp]
     L.esrk_mlp_forward.restype = st
-    L.esrk_mlp_grad.argtypes = [vp, vp, vp, C.c_int, vp, vp, vp]
+    L.esrk_mlp_grad.argtypes = [vp, vp, vp, C.c_int, vp, vp, vp, vp]
     L.esrk_mlp_grad.restype = st
+    L.esrk_mlp_grad_work_size.argtypes = [C.c_int]
+    L.esrk_mlp_grad_work_size.restype = C.c_size_t
     L.esrk_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, vp]
     L.esrk_mlp_adam.restype = st
     L.esrk_mlp_prepare.argtypes = [vp, vp, vp, C.c_int, C.c_int, vp, vp, vp]
@@ -215,6 +217,8 @@ class Context:
                "esrk_set_step_model")
 
     def step(self, u, t, dt=0.0, gamma_k=None, stats=None, stream=None):
+        if stats is not None and not isinstance(stats, int) and stats.numel() < 6:
+            raise ValueError("stats needs 6 float64 entries")
         _check(load().esrk_step(self._h, _ptr(u), _ptr(t), float(dt), _ptr(gamma_k),
                                 _ptr(stats), _stream(stream)), "esrk_step")
 
@@ -280,10 +284,21 @@ def mlp_forward(model, x_norm, y, stream=None):
            "esrk_mlp_forward")
 
 
-def mlp_grad(model, x_norm, t_norm, grad, loss=None, stream=None):
+def mlp_grad_work_size(B):
+    return int(load().esrk_mlp_grad_work_size(int(B)))
+
+
+def mlp_grad(model, x_norm, t_norm, grad, loss=None, work=None, stream=None):
+    """work: device float buffer of mlp_grad_work_size(B) entries (allocated
+    here with torch when not given)."""
     B = t_norm.numel()
+    if work is None:
+        import torch
+        work = torch.empty(mlp_grad_work_size(B), dtype=torch.float32, device=model.device)
+    elif not isinstance(work, int) and work.numel() < mlp_grad_work_size(B):
+        raise ValueError("work buffer too small")
     _check(load().esrk_mlp_grad(_ptr(model), _ptr(x_norm), _ptr(t_norm), B, _ptr(grad),
-                                _ptr(loss), _stream(stream)), "esrk_mlp_grad")
+                                _ptr(loss), _ptr(work), _stream(stream)), "esrk_mlp_grad")
 
 
 def mlp_adam(model, grad, m, v, step, lr, stream=None):

@@ -91,6 +91,7 @@ def train(runs, steps: int = 2000, batch: int = 4096, lr: float = 1e-3, seed: in
     S = x_tr.shape[0]
     B = min(batch, S)
     perm, pos = None, S
+    work = torch.empty(esrk.mlp_grad_work_size(B), dtype=torch.float32, device=dev)
     hist = {"train": [], "val": []}
     for it in range(1, steps + 1):
         if pos + B > S:
@@ -100,7 +101,7 @@ def train(runs, steps: int = 2000, batch: int = 4096, lr: float = 1e-3, seed: in
         pos += B
         xb = x_tr.index_select(0, idx).contiguous()
         tb = t_tr.index_select(0, idx).contiguous()
-        esrk.mlp_grad(model, xb, tb, grad, loss)
+        esrk.mlp_grad(model, xb, tb, grad, loss, work)
         esrk.mlp_adam(model, grad, m, v, it, lr)
         if log_every and (it % log_every == 0 or it == steps):
             hist["train"].append((it, float(loss.item())))

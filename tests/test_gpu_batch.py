@@ -50,7 +50,7 @@ def test_batch_step_equals_single_steps(precision, tableau):
         ctx = esrk.Context(cfgs[s])
         us = torch.as_tensor(states[s], device="cuda").clone()
         ts = torch.zeros(1, dtype=torch.float64, device="cuda")
-        st = torch.zeros(4, dtype=torch.float64, device="cuda")
+        st = torch.zeros(6, dtype=torch.float64, device="cuda")
         singles.append((ctx, us, ts, st))
     for step in range(3):
         b.step(u, t, g)
@@ -118,3 +118,71 @@ def test_batch_rejects_mixed_degree_and_3d():
     c3 = esrk.make_config(3, 3, (2, 2, 2), (0, 0, 0), (1, 1, 1))
     with pytest.raises(esrk.EsrkError):
         esrk.Batch([c3])
+
+
+def test_fp32_flux_relaxation_on_shear_layers(capsys):
+    """Relaxation of FP32-flux increments on a Kelvin-Helmholtz shear layer,
+    against the oracle's FP64 relaxation of the same increments.  The GPU
+    takes the FP32 rounding level 64 eps_32 (sum M |w du| + |deta|) as the
+    noise level of the activity test: elements whose curvature r(1) - phi(0)
+    is clearly below it are inactive, elements clearly above it get the
+    oracle's gamma_k (same increments, so to the FP64 root tolerance and
+    conditioning), and the global gamma stays near 1 (with the FP64 noise
+    level, FP32 rounding in quiet elements used to set gamma ~ 1e-3)."""
+    import oracle as O
+    from tests.oracle_helpers import orc_mesh
+    from tests.test_gpu_parity import relax_tolerance
+
+    ms = I.kh_mesh(32, 3)
+    m = orc_mesh(O, ms)
+    u = I.kh_state(ms, 0.01, 2)
+    ctx = esrk.Context(esrk.make_config(2, 3, ms.nel, ms.lo, ms.hi, precision=esrk.FP32_FLUX))
+    dt = O.cfl_dt(m, u, 0.5)
+    eps_ratio = float(np.finfo(np.float32).eps / np.finfo(np.float64).eps)
+    ud = torch.as_tensor(u, device="cuda")
+    ya, yb = torch.empty_like(ud), torch.empty_like(ud)
+    du = torch.zeros_like(ud)
+    deta = torch.zeros(ctx.ne, dtype=torch.float64, device="cuda")
+    ctx.rk_stage(0, dt, ud, ud, ya, du, deta)
+    ctx.rk_stage(1, dt, ud, ya, yb, du, deta)
+    ctx.rk_stage(2, dt, ud, yb, None, du, deta)
+    gk = torch.zeros(ctx.ne, dtype=torch.float64, device="cuda")
+    gam = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.local_relaxation_solve(ud, du, deta, gk, gam)
+    assert ctx.sync_status()[0] == 0
+    g = gk.cpu().numpy()
+    ref = O.local_relaxation_solve(m, u, du.cpu().numpy(), deta.cpu().numpy())
+    assert ref["rc"] == 0
+    noise32 = ref["noise"] * eps_ratio
+    quiet = ref["curv"] <= 0.5 * noise32
+    resolved = ref["curv"] >= 2.0 * noise32
+    assert np.all(np.isinf(g[quiet]))
+    assert resolved.any() and np.all(np.isfinite(g[resolved]))
+    tol = relax_tolerance(ref)[resolved]
+    err = np.abs(g[resolved] - ref["gamma_k"][resolved])
+    assert np.all(err <= tol), err.max()
+    gmin = float(gam.item())
+    assert 0.9 < gmin <= 1.1
+    with capsys.disabled():
+        print("\n[KH 32^2 p3 FP32 flux] gamma", gmin, "inactive", int(np.isinf(g).sum()),
+              "resolved", int(resolved.sum()), "oracle FP64-noise gamma", ref["gamma"])
+
+
+def test_fp32_batch_gammas_near_one():
+    """The 256-simulation KH batch recipe (first 16 simulations): with FP32
+    flux, every simulation's relaxation parameter stays near 1 as in FP64."""
+    specs = I.kh_batch_specs(256, seed=0)[:16]
+    cfgs, states = [], []
+    for nel, amp, k in specs:
+        ms = I.kh_mesh(nel, 3)
+        cfgs.append(esrk.make_config(2, 3, ms.nel, ms.lo, ms.hi, precision=esrk.FP32_FLUX))
+        states.append(I.kh_state(ms, amp, k))
+    b = esrk.Batch(cfgs)
+    u = packed(b, states)
+    t = torch.zeros(b.nsims, dtype=torch.float64, device="cuda")
+    g = torch.zeros(b.nsims, dtype=torch.float64, device="cuda")
+    for _ in range(6):
+        b.step(u, t, g)
+        torch.cuda.synchronize()
+        assert b.sync_status()[0] == 0
+        assert float(g.min().item()) > 0.9, g.cpu().numpy()
