@@ -14,15 +14,19 @@
 //                 registers, theta for every node -> theta buffer (T precision);
 //   visc_kernel : g_m at the element's nodes into LDS (from u and theta), g_m of
 //                 the face neighbours in registers, Visc -> visc buffer (FP64) and
-//                 the element's viscous entropy dissipation.
+//                 the element's viscous entropy dissipation; in FP32 mode the
+//                 applies D g_m run as one small GEMM per block on the MFMA units.
 // The fused stage kernel adds the visc buffer to the inviscid right-hand side.
 #include <type_traits>
 
 #include "device_math.h"
 #include "internal.h"
 
-// 1: in FP32 mode the derivative applies D (.) along each direction run on the
-// matrix cores (v_mfma_f32_4x4x1f32, 16 blocks); 0: VALU loops as in FP64.
+// 1: in FP32 mode the derivative applies of the viscous divergence (D g_m
+// along each direction m) run on the matrix cores (v_mfma_f32_4x4x1f32, 16
+// blocks); 0: VALU loops as in FP64.  The gradient kernel keeps VALU applies:
+// with the extra LDS round trip and barrier its MFMA form measured 12-20%
+// slower (one apply per field instead of one per field and direction).
 #ifndef ESRK_NS_MFMA
 #define ESRK_NS_MFMA 1
 #endif
@@ -258,21 +262,6 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
     }
   }
   __syncthreads();
-  if constexpr (kUseMfma<T>) {
-    __shared__ float sout[DIM * NV * E * ND];
-    dapply_mfma<DIM, N, E, NV>(sw, 0, sout, mp.D2, G::THREADS);
-    __syncthreads();
-    if (!valid) return;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const T metric = T(mp.two_over_h[d]);
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-        theta[((long long)d * NV + v) * Ntot + (long long)k * ND + i] =
-            metric * (sout[(d * NV + v) * E * ND + e * ND + i] + lift[d][v]);
-    }
-    return;
-  }
   if (!valid) return;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
