@@ -36,35 +36,40 @@ __device__ __forceinline__ unsigned long long bitsd(double d) {
   return (unsigned long long)__double_as_longlong(d);
 }
 
-// h(1+t) = t - log1p(t) = sum_{n>=2} (-1)^n t^n / n
-__device__ __forceinline__ double h_rel(double t) {
-  if (fabs(t) < 1e-2) {
-    double s = -1.0 / 9.0;
-    s = s * t + 1.0 / 8.0;
-    s = s * t - 1.0 / 7.0;
-    s = s * t + 1.0 / 6.0;
-    s = s * t - 1.0 / 5.0;
-    s = s * t + 1.0 / 4.0;
-    s = s * t - 1.0 / 3.0;
-    s = s * t + 1.0 / 2.0;
-    return s * t * t;
-  }
-  return t - log1p(t);
+// h(1+t) = t - log1p(t) = sum_{n>=2} (-1)^n t^n / n and
+// k(1+t) = (1+t) log1p(t) - t = sum_{n>=2} (-1)^n t^n / (n (n-1)), from their
+// series for |t| < 0.1 (16 terms: first dropped term below 1.2e-17 of the
+// leading one; 8 terms when every lane of the wave has |t| < 1e-2) and from
+// log1p beyond.  The coefficients sit in constant memory, so the kernels take
+// them as scalar-register FMA operands (as literals they were rematerialized
+// into vector registers with two moves per use).
+constexpr int kRelTerms = 16;
+__constant__ double kHRel[kRelTerms] = {
+    1.0 / 2, -1.0 / 3, 1.0 / 4, -1.0 / 5, 1.0 / 6, -1.0 / 7, 1.0 / 8, -1.0 / 9,
+    1.0 / 10, -1.0 / 11, 1.0 / 12, -1.0 / 13, 1.0 / 14, -1.0 / 15, 1.0 / 16, -1.0 / 17};
+__constant__ double kKRel[kRelTerms] = {
+    1.0 / 2, -1.0 / 6, 1.0 / 12, -1.0 / 20, 1.0 / 30, -1.0 / 42, 1.0 / 56, -1.0 / 72,
+    1.0 / 90, -1.0 / 110, 1.0 / 132, -1.0 / 156, 1.0 / 182, -1.0 / 210, 1.0 / 240,
+    -1.0 / 272};
+
+template <int K>
+__device__ __forceinline__ double rel_series(const double* c, double t) {
+  double s = c[K - 1];
+#pragma unroll
+  for (int n = K - 2; n >= 0; --n) s = s * t + c[n];
+  return s * t * t;
 }
-// k(1+t) = (1+t) log1p(t) - t = sum_{n>=2} (-1)^n t^n / (n (n-1))
-__device__ __forceinline__ double k_rel(double t) {
-  if (fabs(t) < 1e-2) {
-    double s = -1.0 / 72.0;
-    s = s * t + 1.0 / 56.0;
-    s = s * t - 1.0 / 42.0;
-    s = s * t + 1.0 / 30.0;
-    s = s * t - 1.0 / 20.0;
-    s = s * t + 1.0 / 12.0;
-    s = s * t - 1.0 / 6.0;
-    s = s * t + 1.0 / 2.0;
-    return s * t * t;
+
+// h(1 + tz) and k(1 + tr) of one node; `short_ok` is wave-uniform
+__device__ __forceinline__ void rel_terms(double tz, double tr, bool short_ok, double& h,
+                                          double& k) {
+  if (short_ok) {
+    h = rel_series<8>(kHRel, tz);
+    k = rel_series<8>(kKRel, tr);
+    return;
   }
-  return (1.0 + t) * log1p(t) - t;
+  h = fabs(tz) < 0.1 ? rel_series<kRelTerms>(kHRel, tz) : tz - log1p(tz);
+  k = fabs(tr) < 0.1 ? rel_series<kRelTerms>(kKRel, tr) : (1.0 + tr) * log1p(tr) - tr;
 }
 
 // reciprocal: hardware estimate + two Newton steps (full double precision)
@@ -255,6 +260,9 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
   auto Bsum = [&](double g, bool& ok) -> double {
     double part = 0.0;
     bool bad = false;
+    double tzs[NPL], trs[NPL], dv2s[NPL];
+    bool oks[NPL];
+    bool small = true;
 #pragma unroll
     for (int j = 0; j < NPL; ++j) {
       const double r0 = rho[j];
@@ -274,17 +282,27 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
       const double tp = dp * invp[j];
       const bool okn = (r1 > 0.0) && (1.0 + tp > 0.0);
       if (!okn && has[j]) bad = true;
-      double Dn = 0.0;
-      if (okn) {
-        const double tz = (tp - tr) * r0 * r0 * q;
-        double dv2 = 0.0;
+      const double tz = okn ? (tp - tr) * r0 * r0 * q : 0.0;
+      double dv2 = 0.0;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          const double dv = (g * dm[j][d] - drg * mom[j][d] * invrho[j]) * r0 * q;
-          dv2 += dv * dv;
-        }
-        Dn = r1 * h_rel(tz) * inv_gm1 + r0 * k_rel(tr) + beta[j] * r1 * dv2;
+      for (int d = 0; d < DIM; ++d) {
+        const double dv = (g * dm[j][d] - drg * mom[j][d] * invrho[j]) * r0 * q;
+        dv2 += dv * dv;
       }
+      tzs[j] = tz;
+      trs[j] = okn ? tr : 0.0;
+      dv2s[j] = dv2;
+      oks[j] = okn;
+      small = small && fabs(tzs[j]) < 1e-2 && fabs(trs[j]) < 1e-2;
+    }
+    const bool short_ok = __all(small);
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) {
+      double h, kk;
+      rel_terms(tzs[j], trs[j], short_ok, h, kk);
+      const double r0 = rho[j];
+      const double r1 = r0 + g * dr[j];
+      const double Dn = oks[j] ? r1 * h * inv_gm1 + r0 * kk + beta[j] * r1 * dv2s[j] : 0.0;
       part += Mi[j] * Dn;
     }
     part = seg_sum<G>(bad ? INFINITY : part);

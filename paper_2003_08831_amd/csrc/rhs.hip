@@ -199,6 +199,12 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
     if (k >= md.ne) continue;
     const int stride = (m == 0) ? 1 : (m == 1) ? N : N * N;
     const int base = (l % stride) + (l / stride) * stride * N;
+    // velocity components in the line's frame: component 0 is the line
+    // direction m, then m+1, m+2 (cyclic), so the flux code below is the
+    // direction-0 flux with no per-lane component selection
+    int comp[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) comp[c] = (m + c) % DIM;
 
     // conserved states on both sides of the two faces of the line:
     // side 0 = (-m neighbour's last node | own first node),
@@ -213,10 +219,11 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       const long long g1R = (long long)kp * ND + base;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        qL[0][v] = T(a.y[v * Ntot + g0L]);
-        qR[0][v] = T(a.y[v * Ntot + g0R]);
-        qL[1][v] = T(a.y[v * Ntot + g1L]);
-        qR[1][v] = T(a.y[v * Ntot + g1R]);
+        const int f = (v == 0 || v == NV - 1) ? v : 1 + comp[v - 1];
+        qL[0][v] = T(a.y[f * Ntot + g0L]);
+        qR[0][v] = T(a.y[f * Ntot + g0R]);
+        qL[1][v] = T(a.y[f * Ntot + g1L]);
+        qR[1][v] = T(a.y[f * Ntot + g1R]);
       }
     };
     if (ESRK_RHS_EARLY_FACE_LOADS) load_faces();
@@ -228,7 +235,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       const int slot = e * NDP + node + node / N;
       P[q].rho = sp[C::IR * ENP + slot];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) P[q].v[d] = sp[(C::IV + d) * ENP + slot];
+      for (int d = 0; d < DIM; ++d) P[q].v[d] = sp[(C::IV + comp[d]) * ENP + slot];
       P[q].beta = sp[C::IB * ENP + slot];
       P[q].v2 = sp[C::IV2 * ENP + slot];
     }
@@ -245,7 +252,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
         const PairMeans<T> mn =
             pair_means<T, true>(P[p0].rho, P[p1].rho, P[p0].beta, P[p1].beta);
         T F[NV];
-        ec_flux_from_means<T, DIM>(m, P[p0], P[p1], mn, half_inv_gm1, F);
+        ec_flux_from_means<T, DIM>(0, P[p0], P[p1], mn, half_inv_gm1, F);
         const T d01 = T(mp.D2[p0 * N + p1]), d10 = T(mp.D2[p1 * N + p0]);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -274,7 +281,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       T pl, pr;
       prim_from_cons<T, DIM>(ql, gg, Pl, pl);
       prim_from_cons<T, DIM>(qr, gg, Pr, pr);
-      interface_flux<T, DIM>(m, Pl, ql, Pr, qr, gg, half_inv_gm1, lam_scale, F);
+      interface_flux<T, DIM>(0, Pl, ql, Pr, qr, gg, half_inv_gm1, lam_scale, F);
       const T sg = side ? iw : -iw;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -291,7 +298,10 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       const int node = base + q * stride;
       const int slot = e * NDP + node + node / N;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sacc[(m * NV + v) * ENP + slot] = metric_m * acc[q][v];
+      for (int v = 0; v < NV; ++v) {
+        const int f = (v == 0 || v == NV - 1) ? v : 1 + comp[v - 1];
+        sacc[(m * NV + f) * ENP + slot] = metric_m * acc[q][v];
+      }
     }
   }
   __syncthreads();
