@@ -150,7 +150,7 @@ __device__ __forceinline__ void entropy_vars(const T* q, T gg, T* w) {
   }
   const T p = (gg - T(1)) * (q[DIM + 1] - T(0.5) * rho * v2);
   const T rp = rho * rcp(p);  // rho / p = 2 beta
-  const T s = log(p) - gg * log(rho);
+  const T s = log_d(p) - gg * log_d(rho);
   w[0] = (gg - s) * rcp(gg - T(1)) - T(0.5) * rp * v2;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) w[1 + k] = rp * vel[k];

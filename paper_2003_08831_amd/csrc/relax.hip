@@ -22,6 +22,7 @@
 // than tol * max(1, gamma); the lower end (phi <= 0) is returned.
 #include <cfloat>
 
+#include "device_math.h"
 #include "internal.h"
 
 namespace esrk {
@@ -220,7 +221,7 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
     }
     Mi[j] = has[j] ? M : 0.0;
     // w(u_old).du and its round-off scale
-    const double s_phys = log(p) - gg * log(rho[j]);
+    const double s_phys = log_d(p) - gg * log_d(rho[j]);
     const double v2 = mm * invrho[j] * invrho[j];
     double t = ((gg - s_phys) * inv_gm1 - beta[j] * v2) * dr[j];
     double sc = fabs(t);

@@ -14,13 +14,15 @@
 // and, in stage mode, the Runge-Kutta update (Sec. 2, Runge-Kutta example).
 //
 // Mapping: one block holds E elements.  Phase 0: one thread per node stages the
-// node primitives (rho, v, beta = rho/2p, ln rho, ln beta, |v|^2, c) in LDS
-// with coalesced SoA loads.  Phase 1: one thread per (element, direction,
-// line) evaluates every unordered node pair of its line once (symmetric flux,
-// scattered to both nodes with 2 D_ab and 2 D_ba) plus the two interface fluxes
-// at the line ends, and writes the line's contribution to a per-direction LDS
-// accumulator.  Phase 2: one thread per node sums the directions, writes the
-// outputs and the per-element entropy-rate partials.
+// node primitives (rho, v, beta = rho/2p, |v|^2) in LDS with coalesced SoA
+// loads.  Phase 1a: one thread per (element, direction, line) evaluates every
+// unordered node pair of its line once (symmetric flux, scattered to both
+// nodes with 2 D_ab and 2 D_ba) and writes the line's contribution to a
+// per-direction LDS accumulator.  Phase 1b: one thread per (line, end) adds
+// the interface flux at that end.  Phase 2: one thread per node sums the
+// directions, writes the outputs and the per-element entropy-rate partials.
+// Splitting 1a and 1b keeps the register peak at the larger of the two
+// phases (3-D p=3 FP64: about 120 VGPRs instead of about 250 for both in one).
 #include "device_math.h"
 #include "internal.h"
 
@@ -38,11 +40,6 @@
 #endif
 #ifndef ESRK_RHS_WAVES_PER_EU
 #define ESRK_RHS_WAVES_PER_EU 0
-#endif
-// 1: load the interface states before the volume pairs (latency hiding, more
-// registers); 0: load them just before the interface fluxes.
-#ifndef ESRK_RHS_EARLY_FACE_LOADS
-#define ESRK_RHS_EARLY_FACE_LOADS 0
 #endif
 
 namespace esrk {
@@ -62,8 +59,11 @@ struct RhsCfg {
   // LDS slot of node i: i + i/N, so that lines along any direction spread
   // over the banks (element stride NDP)
   static constexpr int NDP = G::ND + G::ND / N;
+  // the direction accumulators reuse the primitives' slots (phase 1a reads
+  // the primitives into registers before any accumulator is written)
+  static constexpr int SLOTS = NP > DIM * G::NV ? NP : DIM * G::NV;
   static constexpr int LDS_PER_ELEM =
-      NDP * (int)((NP + DIM * G::NV) * sizeof(T)) + G::ND * (int)sizeof(double);
+      NDP * SLOTS * (int)sizeof(T) + G::ND * (int)sizeof(double);
   static constexpr int BUDGET = ESRK_RHS_LDS_KB * 1024;
   static constexpr int E_TASK =
       (ESRK_RHS_TARGET_TASKS / G::TASKS) > 0 ? ESRK_RHS_TARGET_TASKS / G::TASKS : 1;
@@ -82,6 +82,8 @@ struct RhsShape {
   static constexpr int RAW = E * G::TASKS;
   static constexpr int THREADS = ((RAW < 64 ? 64 : RAW) + 63) / 64 * 64;
   static constexpr int SP = NP * ENP, SACC = DIM * G::NV * ENP;
+  static constexpr int SBUF = SP > SACC ? SP : SACC;  // primitives, then accumulators
+  static_assert(THREADS >= RAW, "one line task per thread");
 };
 
 __device__ __forceinline__ void latch(DevScalars* s, int code, long long elem) {
@@ -189,14 +191,17 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
   }
   __syncthreads();
 
-  // ---- phase 1: line tasks (volume pairs + the two interface fluxes) ----
-  for (int task = tid; task < E * G::TASKS; task += TH) {
+  // ---- phase 1a: line tasks (volume pairs) ----
+  // One task per thread.  The primitives of the line go to registers, then a
+  // barrier: the accumulators written below overwrite the primitives' slots.
+  {
+    const int task = tid;
     const int e = task / G::TASKS;
     const int r = task - e * G::TASKS;
     const int m = r / G::NL;
     const int l = r - m * G::NL;
     const int k = k0 + e;
-    if (k >= md.ne) continue;
+    const bool has = task < E * G::TASKS && k < md.ne;
     const int stride = (m == 0) ? 1 : (m == 1) ? N : N * N;
     const int base = (l % stride) + (l / stride) * stride * N;
     // velocity components in the line's frame: component 0 is the line
@@ -206,101 +211,113 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
 #pragma unroll
     for (int c = 0; c < DIM; ++c) comp[c] = (m + c) % DIM;
 
-    // conserved states on both sides of the two faces of the line:
-    // side 0 = (-m neighbour's last node | own first node),
-    // side 1 = (own last node | +m neighbour's first node)
-    T qL[2][NV], qR[2][NV];
-    auto load_faces = [&]() {
-      const int km = neighbour<DIM>(md, k, m, -1);
-      const int kp = neighbour<DIM>(md, k, m, +1);
-      const long long g0L = (long long)km * ND + base + (N - 1) * stride;
-      const long long g0R = (long long)k * ND + base;
-      const long long g1L = (long long)k * ND + base + (N - 1) * stride;
-      const long long g1R = (long long)kp * ND + base;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int f = (v == 0 || v == NV - 1) ? v : 1 + comp[v - 1];
-        qL[0][v] = T(a.y[f * Ntot + g0L]);
-        qR[0][v] = T(a.y[f * Ntot + g0R]);
-        qL[1][v] = T(a.y[f * Ntot + g1L]);
-        qR[1][v] = T(a.y[f * Ntot + g1R]);
-      }
-    };
-    if (ESRK_RHS_EARLY_FACE_LOADS) load_faces();
-
     Prim<T, DIM> P[N];
+    if (has) {
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-      const int node = base + q * stride;
-      const int slot = e * NDP + node + node / N;
-      P[q].rho = sp[C::IR * ENP + slot];
+      for (int q = 0; q < N; ++q) {
+        const int node = base + q * stride;
+        const int slot = e * NDP + node + node / N;
+        P[q].rho = sp[C::IR * ENP + slot];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) P[q].v[d] = sp[(C::IV + comp[d]) * ENP + slot];
-      P[q].beta = sp[C::IB * ENP + slot];
-      P[q].v2 = sp[C::IV2 * ENP + slot];
+        for (int d = 0; d < DIM; ++d) P[q].v[d] = sp[(C::IV + comp[d]) * ENP + slot];
+        P[q].beta = sp[C::IB * ENP + slot];
+        P[q].v2 = sp[C::IV2 * ENP + slot];
+      }
     }
-    T acc[N][NV];
+    __syncthreads();
+    if (has) {
+      T acc[N][NV];
 #pragma unroll
-    for (int q = 0; q < N; ++q)
+      for (int q = 0; q < N; ++q)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[q][v] = T(0);
+        for (int v = 0; v < NV; ++v) acc[q][v] = T(0);
 
 #pragma unroll
-    for (int p0 = 0; p0 < N; ++p0) {
+      for (int p0 = 0; p0 < N; ++p0) {
 #pragma unroll
-      for (int p1 = p0 + 1; p1 < N; ++p1) {
-        const PairMeans<T> mn =
-            pair_means<T, true>(P[p0].rho, P[p1].rho, P[p0].beta, P[p1].beta);
-        T F[NV];
-        ec_flux_from_means<T, DIM>(0, P[p0], P[p1], mn, half_inv_gm1, F);
-        const T d01 = T(mp.D2[p0 * N + p1]), d10 = T(mp.D2[p1 * N + p0]);
+        for (int p1 = p0 + 1; p1 < N; ++p1) {
+          const PairMeans<T> mn =
+              pair_means<T, true>(P[p0].rho, P[p1].rho, P[p0].beta, P[p1].beta);
+          T F[NV];
+          ec_flux_from_means<T, DIM>(0, P[p0], P[p1], mn, half_inv_gm1, F);
+          const T d01 = T(mp.D2[p0 * N + p1]), d10 = T(mp.D2[p1 * N + p0]);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            acc[p0][v] += d01 * F[v];
+            acc[p1][v] += d10 * F[v];
+          }
+        }
+      }
+
+      const T metric_m = (m == 0) ? T(md.two_over_h[0])
+                                  : (m == 1) ? T(md.two_over_h[1]) : T(md.two_over_h[2]);
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        const int node = base + q * stride;
+        const int slot = e * NDP + node + node / N;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          acc[p0][v] += d01 * F[v];
-          acc[p1][v] += d10 * F[v];
+          const int f = (v == 0 || v == NV - 1) ? v : 1 + comp[v - 1];
+          sacc[(m * NV + f) * ENP + slot] = metric_m * acc[q][v];
         }
       }
     }
+  }
+  __syncthreads();
 
-    // interface fluxes at both ends of the line.  Both faces go through one
-    // code path (the loop is not unrolled) with identical operands on the two
-    // elements that share a face, so both compute bit-identical f* and the
-    // scheme stays conservative to round-off of the sums.
+  // ---- phase 1b: face tasks (one interface flux each) ----
+  // Task (line, side): side 0 is the line's -m face (the -m neighbour's last
+  // node | own first node), side 1 its +m face (own last node | the +m
+  // neighbour's first node).  Every face goes through this one loop body (not
+  // unrolled) with the same operand order on both elements that share it, so
+  // both compute a bit-identical f* and the scheme stays conservative to
+  // round-off of the sums.  Kept apart from the volume pairs, neither phase
+  // holds the other's registers.
+  {
     const T lam_scale = T(mp.lambda_scale);
     const T iw = T(mp.inv_w_end);
-    if (!ESRK_RHS_EARLY_FACE_LOADS) load_faces();
 #pragma unroll 1
-    for (int side = 0; side < 2; ++side) {
+    for (int ft = tid; ft < E * 2 * G::TASKS; ft += TH) {
+      // all -m faces first, then all +m faces: neighbouring lanes take
+      // neighbouring lines (coalesced trace loads)
+      const int side = ft >= E * G::TASKS;
+      const int task = side ? ft - E * G::TASKS : ft;
+      const int e = task / G::TASKS;
+      const int r = task - e * G::TASKS;
+      const int m = r / G::NL;
+      const int l = r - m * G::NL;
+      const int k = k0 + e;
+      if (k >= md.ne) continue;
+      const int stride = (m == 0) ? 1 : (m == 1) ? N : N * N;
+      const int base = (l % stride) + (l / stride) * stride * N;
+      int comp[DIM];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) comp[c] = (m + c) % DIM;
+      const int kn = neighbour<DIM>(md, k, m, side ? +1 : -1);
+      const int own = base + (side ? (N - 1) * stride : 0);
+      const int nbr = base + (side ? 0 : (N - 1) * stride);
+      const long long gL = side ? (long long)k * ND + own : (long long)kn * ND + nbr;
+      const long long gR = side ? (long long)kn * ND + nbr : (long long)k * ND + own;
       T ql[NV], qr[NV], F[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        ql[v] = side ? qL[1][v] : qL[0][v];
-        qr[v] = side ? qR[1][v] : qR[0][v];
+        const int f = (v == 0 || v == NV - 1) ? v : 1 + comp[v - 1];
+        ql[v] = T(a.y[f * Ntot + gL]);
+        qr[v] = T(a.y[f * Ntot + gR]);
       }
       Prim<T, DIM> Pl, Pr;
       T pl, pr;
       prim_from_cons<T, DIM>(ql, gg, Pl, pl);
       prim_from_cons<T, DIM>(qr, gg, Pr, pr);
       interface_flux<T, DIM>(0, Pl, ql, Pr, qr, gg, half_inv_gm1, lam_scale, F);
-      const T sg = side ? iw : -iw;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const T c = sg * F[v];
-        acc[0][v] += side ? T(0) : c;
-        acc[N - 1][v] += side ? c : T(0);
-      }
-    }
-
-    const T metric_m = (m == 0) ? T(md.two_over_h[0])
-                                : (m == 1) ? T(md.two_over_h[1]) : T(md.two_over_h[2]);
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      const int node = base + q * stride;
-      const int slot = e * NDP + node + node / N;
+      const T metric_m = (m == 0) ? T(md.two_over_h[0])
+                                  : (m == 1) ? T(md.two_over_h[1]) : T(md.two_over_h[2]);
+      const T sg = metric_m * (side ? iw : -iw);
+      const int slot = e * NDP + own + own / N;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const int f = (v == 0 || v == NV - 1) ? v : 1 + comp[v - 1];
-        sacc[(m * NV + f) * ENP + slot] = metric_m * acc[q][v];
+        sacc[(m * NV + f) * ENP + slot] += sg * F[v];
       }
     }
   }
@@ -333,7 +350,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       uo[v] = want_uold ? a.u_old[v * Ntot + gi] : 0.0;
-      yv[v] = (want_y || sizeof(T) != sizeof(double)) ? a.y[v * Ntot + gi] : 0.0;
+      yv[v] = a.y[v * Ntot + gi];
       dp[v] = want_du ? a.du[v * Ntot + gi] : 0.0;
     }
     double kv[NV];
@@ -346,14 +363,9 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       if (a.visc) kv[v] += a.visc[v * Ntot + gi];
     }
     // entropy variables in FP64: w = [(g - s)/(g-1) - beta |v|^2, 2 beta v, -2 beta]
+    // (primitives recomputed from y: their LDS slots now hold the accumulators)
     double rho, beta, v2, vel[DIM];
-    if constexpr (sizeof(T) == sizeof(double)) {
-      rho = sp[C::IR * ENP + slot];
-      beta = sp[C::IB * ENP + slot];
-      v2 = sp[C::IV2 * ENP + slot];
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) vel[d] = sp[(C::IV + d) * ENP + slot];
-    } else {
+    {
       Prim<double, DIM> P;
       double p;
       prim_from_cons<double, DIM>(yv, ggd, P, p);
@@ -363,7 +375,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
 #pragma unroll
       for (int d = 0; d < DIM; ++d) vel[d] = P.v[d];
     }
-    const double lnr = log(rho), lnb = log(beta);
+    const double lnr = log_d(rho), lnb = log_d(beta);
     const double s_phys = (1.0 - ggd) * lnr - 0.6931471805599453 - lnb;  // ln p - g ln rho
     double wdot = ((ggd - s_phys) * inv_gm1d - beta * v2) * kv[0];
 #pragma unroll
@@ -376,7 +388,12 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       for (int d = 0; d < DIM; ++d) {
         const int im = ii % N;
         ii /= N;
-        M *= md.half_h[d] * mp.w[im];
+        // select chain: a runtime index into the kernel-argument array would
+        // copy the array to scratch memory
+        double wq = mp.w[0];
+#pragma unroll
+        for (int t = 1; t < N; ++t) wq = (im == t) ? mp.w[t] : wq;
+        M *= md.half_h[d] * wq;
       }
     }
     sred[idx] = M * wdot;
@@ -423,12 +440,15 @@ __global__ void __launch_bounds__((RhsShape<DIM, N, T, RhsCfg<DIM, N, T>::E>::TH
     rhs_kernel(const MeshParams mp, const RhsArgs a) {
   constexpr int E = RhsCfg<DIM, N, T>::E;
   using S = RhsShape<DIM, N, T, E>;
-  __shared__ T sp[S::SP];
-  __shared__ T sacc[S::SACC];
+  __shared__ T sbuf[S::SBUF];
   __shared__ double sred[S::EN];
   __shared__ double s_dt;
-  const MeshDims md = dims_of(mp);
-  rhs_block<DIM, N, T, E>(mp, md, a, blockIdx.x * E, sp, sacc, sred, &s_dt);
+  // mesh sizes in LDS: the direction-dependent lookups (metric, elements per
+  // direction) become LDS reads instead of a private copy in scratch memory
+  __shared__ MeshDims smd;
+  if (threadIdx.x == 0) smd = dims_of(mp);
+  __syncthreads();
+  rhs_block<DIM, N, T, E>(mp, smd, a, blockIdx.x * E, sbuf, sbuf, sred, &s_dt);
 }
 
 // Batched form: the blocks walk a work list of (simulation, first element)
@@ -441,8 +461,7 @@ __global__ void __launch_bounds__((RhsShape<DIM, N, T, E>::THREADS))
                      const int2* __restrict__ items, int nitems, double* dt_sims,
                      const double* dt_sims_in) {
   using S = RhsShape<DIM, N, T, E>;
-  __shared__ T sp[S::SP];
-  __shared__ T sacc[S::SACC];
+  __shared__ T sbuf[S::SBUF];
   __shared__ double sred[S::EN];
   __shared__ double s_dt;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -459,7 +478,7 @@ __global__ void __launch_bounds__((RhsShape<DIM, N, T, E>::THREADS))
     a.dt_dev = dt_sims_in ? dt_sims_in + w.x : nullptr;
     a.dt_store = dt_sims ? dt_sims + w.x : nullptr;
     a.elem_base = P.elem_base;
-    rhs_block<DIM, N, T, E>(mp, P.md, a, w.y, sp, sacc, sred, &s_dt);
+    rhs_block<DIM, N, T, E>(mp, P.md, a, w.y, sbuf, sbuf, sred, &s_dt);
     __syncthreads();
   }
 }
