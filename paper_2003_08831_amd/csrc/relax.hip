@@ -458,6 +458,15 @@ __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const R
   const MeshDims md = dims_of(mp);
   relax_block<DIM, N, NET>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB, blockIdx.x, 0);
 }
+// The same with the register budget of four waves per SIMD (one node per
+// lane: 3-D p=3 fits with a few spilled setup values, so all blocks of a
+// 16^3 mesh are resident at once).
+template <int DIM, int N, bool NET>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+    relax_kernel_w4(const MeshParams mp, const RelaxArgs a) {
+  const MeshDims md = dims_of(mp);
+  relax_block<DIM, N, NET>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB, blockIdx.x, 0);
+}
 
 // Batched form over (simulation, first element) items; partial per item.
 template <int DIM, int N>
@@ -509,6 +518,9 @@ static hipError_t relax_one(const MeshParams& mp, const RelaxArgs& a, hipStream_
   const int blocks = (mp.ne + C::EPB - 1) / C::EPB;
   if (a.model || a.feats)
     hipLaunchKernelGGL((relax_kernel<DIM, N, true>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
+  else if constexpr (DIM == 3 && C::NPL == 1)
+    hipLaunchKernelGGL((relax_kernel_w4<DIM, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, mp,
+                       a);
   else
     hipLaunchKernelGGL((relax_kernel<DIM, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
   return hipGetLastError();

@@ -107,6 +107,18 @@ __device__ __forceinline__ int neighbour(const MeshDims& md, int k, int m, int d
   return c[0] + md.nel[0] * (c[1] + md.nel[1] * c[2]);
 }
 
+// First node of line l along direction m (lines of a direction numbered
+// lexicographically over the other directions); divisions by the compile-time
+// N only.
+template <int DIM, int N>
+__device__ __forceinline__ int line_base(int m, int l) {
+  if (DIM == 1) return 0;
+  if (DIM == 2) return m == 0 ? l * N : l;
+  const int b0 = l * N;                       // m = 0: l = i1 + N i2
+  const int b1 = (l % N) + (l / N) * N * N;   // m = 1: l = i0 + N i2
+  return m == 0 ? b0 : (m == 1 ? b1 : l);     // m = 2: l = i0 + N i1
+}
+
 // Interface flux f* in direction m between a left and a right node, given
 // both primitive sets and conserved states.
 template <typename T, int DIM>
@@ -134,7 +146,7 @@ __device__ __forceinline__ void interface_flux(int m, const Prim<T, DIM>& A, con
 template <int DIM, int N, typename T, int E>
 __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& md,
                                           const RhsArgs& a, const int k0, T* sp, T* sacc,
-                                          double* sred, double* s_dt) {
+                                          double* sred, double* s_dt, int* snbr) {
   using S = RhsShape<DIM, N, T, E>;
   using C = S;
   using G = Geo<DIM, N>;
@@ -156,6 +168,14 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
 #pragma unroll
     for (int off = 32; off >= 1; off /= 2) mx = fmax(mx, __shfl_xor(mx, off, 64));
     if (tid == 0) *s_dt = md.cfl * md.hmin / (double(mp.n) * mx);
+  }
+
+  // face neighbours of the block's elements (runtime divisions once per element)
+  for (int t = tid; t < E * 2 * DIM; t += TH) {
+    const int e = t / (2 * DIM);
+    const int md_ = (t - e * 2 * DIM) >> 1;
+    const int k = k0 + e < md.ne ? k0 + e : 0;
+    snbr[t] = neighbour<DIM>(md, k, md_, (t & 1) ? +1 : -1);
   }
 
   // ---- phase 0: node primitives into LDS ----
@@ -203,7 +223,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
     const int k = k0 + e;
     const bool has = task < E * G::TASKS && k < md.ne;
     const int stride = (m == 0) ? 1 : (m == 1) ? N : N * N;
-    const int base = (l % stride) + (l / stride) * stride * N;
+    const int base = line_base<DIM, N>(m, l);
     // velocity components in the line's frame: component 0 is the line
     // direction m, then m+1, m+2 (cyclic), so the flux code below is the
     // direction-0 flux with no per-lane component selection
@@ -289,11 +309,11 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       const int k = k0 + e;
       if (k >= md.ne) continue;
       const int stride = (m == 0) ? 1 : (m == 1) ? N : N * N;
-      const int base = (l % stride) + (l / stride) * stride * N;
+      const int base = line_base<DIM, N>(m, l);
       int comp[DIM];
 #pragma unroll
       for (int c = 0; c < DIM; ++c) comp[c] = (m + c) % DIM;
-      const int kn = neighbour<DIM>(md, k, m, side ? +1 : -1);
+      const int kn = snbr[e * 2 * DIM + 2 * m + side];
       const int own = base + (side ? (N - 1) * stride : 0);
       const int nbr = base + (side ? 0 : (N - 1) * stride);
       const long long gL = side ? (long long)k * ND + own : (long long)kn * ND + nbr;
@@ -442,13 +462,14 @@ __global__ void __launch_bounds__((RhsShape<DIM, N, T, RhsCfg<DIM, N, T>::E>::TH
   using S = RhsShape<DIM, N, T, E>;
   __shared__ T sbuf[S::SBUF];
   __shared__ double sred[S::EN];
+  __shared__ int snbr[E * 2 * DIM];
   __shared__ double s_dt;
   // mesh sizes in LDS: the direction-dependent lookups (metric, elements per
   // direction) become LDS reads instead of a private copy in scratch memory
   __shared__ MeshDims smd;
   if (threadIdx.x == 0) smd = dims_of(mp);
   __syncthreads();
-  rhs_block<DIM, N, T, E>(mp, smd, a, blockIdx.x * E, sbuf, sbuf, sred, &s_dt);
+  rhs_block<DIM, N, T, E>(mp, smd, a, blockIdx.x * E, sbuf, sbuf, sred, &s_dt, snbr);
 }
 
 // Batched form: the blocks walk a work list of (simulation, first element)
@@ -463,6 +484,7 @@ __global__ void __launch_bounds__((RhsShape<DIM, N, T, E>::THREADS))
   using S = RhsShape<DIM, N, T, E>;
   __shared__ T sbuf[S::SBUF];
   __shared__ double sred[S::EN];
+  __shared__ int snbr[E * 2 * DIM];
   __shared__ double s_dt;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 w = items[it];
@@ -478,7 +500,7 @@ __global__ void __launch_bounds__((RhsShape<DIM, N, T, E>::THREADS))
     a.dt_dev = dt_sims_in ? dt_sims_in + w.x : nullptr;
     a.dt_store = dt_sims ? dt_sims + w.x : nullptr;
     a.elem_base = P.elem_base;
-    rhs_block<DIM, N, T, E>(mp, P.md, a, w.y, sbuf, sbuf, sred, &s_dt);
+    rhs_block<DIM, N, T, E>(mp, P.md, a, w.y, sbuf, sbuf, sred, &s_dt, snbr);
     __syncthreads();
   }
 }
