@@ -59,6 +59,26 @@ def term_scale(O, ms, u):
     return fmax * metric * opnorm * ms.dim
 
 
+def term_scale_np(O, ms, u):
+    """term_scale with max|f_v,m(u)| taken by numpy over all nodes at once (a
+    tolerance scale, for meshes too large for the per-node oracle calls):
+    f_m = [rho v_m, rho v_m v + p e_m, v_m (E + p)]."""
+    U = np.asarray(u).reshape(ms.nv, -1)
+    rho, E = U[0], U[-1]
+    vel = U[1:1 + ms.dim] / rho
+    p = (ms.gas_gamma - 1.0) * (E - 0.5 * rho * (vel ** 2).sum(axis=0))
+    fmax = np.zeros(ms.nv)
+    for m in range(ms.dim):
+        f = [rho * vel[m]] + [rho * vel[m] * vel[k] + (p if k == m else 0.0)
+                              for k in range(ms.dim)] + [vel[m] * (E + p)]
+        fmax = np.maximum(fmax, np.array([np.abs(fv).max() for fv in f]))
+    D = O.dmat(ms.deg)
+    _, w = O.lgl(ms.deg)
+    metric = max(2.0 * ms.nel[m] / (ms.hi[m] - ms.lo[m]) for m in range(ms.dim))
+    opnorm = np.abs(2.0 * D).sum(axis=1).max() + 1.0 / w[0]
+    return fmax * metric * opnorm * ms.dim
+
+
 def rhs_close(g, o, ms, S, rel=1e-12, cond=1e-14):
     """Component-wise: |g - o| <= rel * max|o_v| + cond * S_v, where S_v is the
     term scale (FP64 evaluations of a cancelling sum differ by ~eps * S_v)."""

@@ -1,0 +1,235 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configuration
+bench.py times (whole esrk_step calls, device CFL step size, RK(4,4) for the
+Taylor-Green runs, SSPRK(3,3) for the vortex and the Kelvin-Helmholtz batch).
+
+* 2-D isentropic vortex 8x8 p=3: all 100 steps, each started from the
+  oracle's state.
+* 3-D Euler Taylor-Green 16^3 p=3: the whole right-hand side against the
+  oracle (FP64 and FP32 flux), two relaxed steps, and 50 free-running steps
+  checked for conservation and total-entropy decay.
+* 3-D Navier-Stokes Taylor-Green 32^3 p=4: the whole right-hand side and the
+  element viscous dissipation against the oracle (FP64), and FP32 (MFMA
+  divergence) conservation.
+* 256-simulation Kelvin-Helmholtz batch: one FP64 batch step, four sampled
+  simulations (one of each size) against oracle steps; FP32 batch steps keep
+  every simulation's gamma near 1.
+Tolerances are those of the small-size parity tests (see test_gpu_parity)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_2003_08831_amd import esrk  # noqa: E402
+from paper_2003_08831_amd import inputs as I  # noqa: E402
+from tests.gpu_helpers import ctx_for, dev, host, normwise, rhs_close, term_scale_np, zeros  # noqa: E402
+from tests.oracle_helpers import node_mass, orc_mesh, view  # noqa: E402
+from tests.test_gpu_parity import RTOL, oracle_step  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_step(ctx, ms, m, tab, u, t_ref, cfl, stats, label):
+    ud = dev(u)
+    t = dev(np.array([t_ref]))
+    u_next, t_next, dt, g, gtol, du = oracle_step(m, tab, u, t_ref, cfl)
+    ctx.step(ud, t, 0.0, None, stats)
+    st = host(stats)
+    assert abs(st[1] - dt) <= 1e-14 * dt, label
+    assert abs(st[0] - g) <= gtol, (label, st[0], g, gtol)
+    got = host(ud).reshape(ms.nv, -1)
+    ref = u_next.reshape(ms.nv, -1)
+    dref = du.reshape(ms.nv, -1)
+    for v in range(ms.nv):
+        tolv = RTOL * np.abs(ref[v]).max() + gtol * np.abs(dref[v]).max()
+        assert np.abs(got[v] - ref[v]).max() <= tolv, (label, v)
+    return u_next, t_next
+
+
+def test_vortex_8x8_p3_all_100_steps():
+    ms = I.vortex_mesh(8, 3)
+    m = orc_mesh(O, ms)
+    ctx = ctx_for(ms, tableau=esrk.SSPRK33, cfl=0.5)
+    stats = zeros(6)
+    u, t = I.vortex_state(ms), 0.0
+    for step in range(100):
+        u, t = _check_step(ctx, ms, m, O.SSPRK33, u, t, 0.5, stats, step)
+    assert ctx.sync_status()[0] == 0
+
+
+@pytest.fixture(scope="module")
+def tgv16():
+    ms = I.tgv_mesh(16, 3)
+    u = I.tgv_state(ms, 0.1)
+    m = orc_mesh(O, ms)
+    ref, ref_eta = O.rhs(m, u)
+    return ms, m, u, ref, ref_eta
+
+
+def test_tgv16_p3_rhs_fp64_and_fp32(tgv16):
+    ms, m, u, ref, ref_eta = tgv16
+    S = term_scale_np(O, ms, u)
+    ctx = ctx_for(ms, tableau=esrk.RK44)
+    out, eta = zeros(u.size), zeros(ctx.ne)
+    ctx.rhs_euler(dev(u), out, eta)
+    assert rhs_close(host(out), ref, ms, S) <= 1.0
+    # element entropy rate: node bounds weighted by M_i |w_v| and summed
+    M = node_mass(O, ms)
+    W = np.stack([O.entropy_vars(3, ms.gas_gamma, view(ms, u)[:, k, i])
+                  for k in range(ms.ne) for i in range(ms.nd)]).T.reshape(ms.nv, ms.ne, ms.nd)
+    R = np.abs(view(ms, ref)).reshape(ms.nv, -1).max(axis=1)
+    node_tol = (RTOL * R + 1e-14 * S)[:, None, None] * np.abs(W)
+    eta_tol = (node_tol.sum(axis=0) * M).sum(axis=1)
+    assert np.all(np.abs(host(eta) - ref_eta) <= eta_tol)
+    # FP32 flux: pointwise error, the right-hand side's integrals, and the
+    # conserved integrals of the state over relaxed steps
+    c32 = ctx_for(ms, tableau=esrk.RK44, precision=esrk.FP32_FLUX)
+    _fp32_checks(c32, ms, u, ref, M, S, steps=5)
+
+
+def _fp32_checks(c32, ms, u, ref, M, S, steps):
+    """FP32 flux differences (and viscous terms): pointwise error within
+    64 eps_32 of the term scale S_v (the FP64 bound is 1e-14 S_v = 45 eps_64;
+    at low Mach the error relative to max|dudt| grows with 2/h: 1.0e-2 on the
+    16^3 mesh, 5e-3 on 3^3); the integral sum M dudt
+    vanishes up to FP32 rounding of the cancelling terms, at most 16 eps_32
+    S_v per unit mass (the D weights are FP32 numbers, so pairs no longer
+    cancel exactly and the error grows with 2/h at low Mach); the conserved
+    integrals sum M u move by at most 1e-5 of sum M |u| over `steps` steps."""
+    ud = dev(u)
+    out32 = zeros(u.size)
+    if ms.mu > 0.0:
+        c32.rhs_ns(ud, out32)
+    else:
+        c32.rhs_euler(ud, out32)
+    g = host(out32).reshape(ms.nv, ms.ne, ms.nd)
+    eps32 = float(np.finfo(np.float32).eps)
+    worst = rhs_close(g.reshape(-1), ref, ms, S, rel=0.0, cond=64 * eps32)
+    assert worst <= 1.0, (worst, normwise(g.reshape(-1), ref, ms.nv))
+    integ = (g * M).sum(axis=(1, 2))
+    assert np.all(np.abs(integ) <= 16 * eps32 * S * M.sum() * ms.ne), (integ, S)
+    U0 = view(ms, u)
+    cons0 = (U0 * M).sum(axis=(1, 2))
+    size = (np.abs(U0) * M).sum(axis=(1, 2))
+    # momentum components share one scale (the TGV's z-momentum is zero)
+    size[1:1 + ms.dim] = size[1:1 + ms.dim].sum()
+    t, stats = zeros(1), zeros(6)
+    for _ in range(steps):
+        c32.step(ud, t, 0.0, None, stats)
+    assert c32.sync_status()[0] == 0
+    cons = (view(ms, host(ud)) * M).sum(axis=(1, 2))
+    assert np.all(np.abs(cons - cons0) <= 1e-5 * size), (cons - cons0) / size
+
+
+def test_tgv16_p3_two_steps(tgv16):
+    ms, m, u, _, _ = tgv16
+    ctx = ctx_for(ms, tableau=esrk.RK44, cfl=0.5)
+    stats = zeros(6)
+    t = 0.0
+    for step in range(2):
+        u, t = _check_step(ctx, ms, m, O.RK44, u, t, 0.5, stats, step)
+    assert ctx.sync_status()[0] == 0
+
+
+def test_tgv16_p3_50_free_steps_conservation_and_entropy(tgv16):
+    ms, m, u0, _, _ = tgv16
+    ctx = ctx_for(ms, tableau=esrk.RK44, cfl=0.5)
+    ud, t, stats = dev(u0), zeros(1), zeros(6)
+    M = node_mass(O, ms)
+    cons0 = (view(ms, u0) * M).sum(axis=(1, 2))
+    sc = (np.abs(view(ms, u0)) * M).sum(axis=(1, 2))
+    sc[1:4] = sc[1:4].sum()  # one momentum scale (the z-momentum is zero)
+    eta_prev = O.elem_entropy(m, u0).sum()
+    for step in range(50):
+        ctx.step(ud, t, 0.0, None, stats)
+        st = host(stats)
+        assert 0.99 < st[0] < 1.01
+        if step % 10 == 9:
+            uh = host(ud)
+            eta = O.elem_entropy(m, uh).sum()
+            assert eta <= eta_prev + 1e-13 * abs(eta_prev), step
+            eta_prev = eta
+    cons = (view(ms, host(ud)) * M).sum(axis=(1, 2))
+    assert np.all(np.abs(cons - cons0) <= 1e-13 * sc)
+    assert ctx.sync_status()[0] == 0
+
+
+def test_ns_tgv32_p4_rhs_and_dissipation():
+    ms = I.tgv_mesh(32, 4, mu=1.0 / 1600.0)
+    u = I.tgv_state(ms, 0.1)
+    m = orc_mesh(O, ms)
+    print("\n[ns 32^3 p4] oracle right-hand sides ...", flush=True)
+    ref, ref_eta, ref_diss = O.rhs(m, u, want_visc=True)
+    m_eu = orc_mesh(O, I.MeshSpec(dim=3, deg=4, nel=ms.nel, lo=ms.lo, hi=ms.hi))
+    ref_eu, _ = O.rhs(m_eu, u)
+    # tolerance scale as in the small NS parity tests: inviscid term scale plus
+    # 100 times the size of the viscous right-hand side
+    S = term_scale_np(O, ms, u) + 100.0 * np.abs((ref - ref_eu).reshape(ms.nv, -1)).max(axis=1)
+    del ref_eu
+    ctx = ctx_for(ms, tableau=esrk.RK44)
+    out, eta, diss = zeros(u.size), zeros(ctx.ne), zeros(ctx.ne)
+    ud = dev(u)
+    ctx.rhs_ns(ud, out, eta, diss)
+    assert rhs_close(host(out), ref, ms, S) <= 1.0
+    d = host(diss)
+    assert np.all(d >= -1e-15 * np.abs(ref_diss).max())
+    np.testing.assert_allclose(d, ref_diss, rtol=1e-11, atol=1e-13 * np.abs(ref_diss).max())
+    del ctx, out, eta, diss
+    # FP32 flux and viscous terms (MFMA divergence)
+    c32 = ctx_for(ms, tableau=esrk.RK44, precision=esrk.FP32_FLUX)
+    _fp32_checks(c32, ms, u, ref, node_mass(O, ms), S, steps=2)
+
+
+def _kh_batch(precision):
+    specs = I.kh_batch_specs(256, seed=0)
+    cfgs, states = [], []
+    for nel, amp, k in specs:
+        ms = I.kh_mesh(nel, 3)
+        cfgs.append(esrk.make_config(2, 3, ms.nel, ms.lo, ms.hi, precision=precision,
+                                     tableau=esrk.SSPRK33, cfl=0.5))
+        states.append(I.kh_state(ms, amp, k))
+    b = esrk.Batch(cfgs)
+    u = torch.zeros(b.len, dtype=torch.float64, device="cuda")
+    for s, st in enumerate(states):
+        u[b.offsets[s]:b.offsets[s] + st.size] = torch.as_tensor(st, device="cuda")
+    return specs, states, b, u
+
+
+def test_kh_batch_256_fp64_step_sampled_against_oracle():
+    specs, states, b, u = _kh_batch(esrk.FP64)
+    t = torch.zeros(b.nsims, dtype=torch.float64, device="cuda")
+    g = torch.zeros(b.nsims, dtype=torch.float64, device="cuda")
+    b.step(u, t, g)
+    assert b.sync_status()[0] == 0
+    uh, gh, th = host(u), host(g), host(t)
+    picked = {}
+    for s, (nel, _, _) in enumerate(specs):
+        picked.setdefault(nel, s)
+    for nel, s in sorted(picked.items()):
+        ms = I.kh_mesh(nel, 3)
+        m = orc_mesh(O, ms)
+        u_next, t_next, dt, gam, gtol, du = oracle_step(m, O.SSPRK33, states[s], 0.0, 0.5)
+        assert abs(gh[s] - gam) <= gtol, (nel, gh[s], gam)
+        assert abs(th[s] - t_next) <= 1e-14 * t_next + gtol * dt
+        got = uh[b.offsets[s]:b.offsets[s] + u_next.size].reshape(ms.nv, -1)
+        ref = u_next.reshape(ms.nv, -1)
+        dref = du.reshape(ms.nv, -1)
+        for v in range(ms.nv):
+            tolv = RTOL * np.abs(ref[v]).max() + gtol * np.abs(dref[v]).max()
+            assert np.abs(got[v] - ref[v]).max() <= tolv, (nel, v)
+
+
+def test_kh_batch_256_fp32_graph_steps():
+    specs, states, b, u = _kh_batch(esrk.FP32_FLUX)
+    t = torch.zeros(b.nsims, dtype=torch.float64, device="cuda")
+    g = torch.zeros(b.nsims, dtype=torch.float64, device="cuda")
+    b.autotune(u)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        b.run_graph(u, t, 5, g, stream=stream)
+    stream.synchronize()
+    assert b.sync_status()[0] == 0
+    gh = host(g)
+    assert np.all((gh > 0.9) & (gh < 1.1)), gh
+    assert np.all(host(t) > 0.0)
