@@ -474,7 +474,11 @@ __global__ void __launch_bounds__(256)
     relax_batch_kernel(const MeshParams mp, const RelaxArgs a0, const SimParams* __restrict__ sims,
                        const int2* __restrict__ items, int nitems) {
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int2 w = items[it];
+    // the item is the same for the whole block: keep it (and everything
+    // derived from it: offsets, pointers, mesh sizes) in scalar registers
+    int2 w = items[it];
+    w.x = __builtin_amdgcn_readfirstlane(w.x);
+    w.y = __builtin_amdgcn_readfirstlane(w.y);
     const SimParams& P = sims[w.x];
     RelaxArgs a = a0;
     a.u_old = a0.u_old + P.base;
@@ -723,7 +727,11 @@ __global__ void __launch_bounds__(256) speed_batch_kernel(const double* u, doubl
                                                           int nitems, int nd, double* parts) {
   __shared__ double sh[4];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int2 w = items[it];
+    // the item is the same for the whole block: keep it (and everything
+    // derived from it: offsets, pointers, mesh sizes) in scalar registers
+    int2 w = items[it];
+    w.x = __builtin_amdgcn_readfirstlane(w.x);
+    w.y = __builtin_amdgcn_readfirstlane(w.y);
     const SimParams& P = sims[w.x];
     const long long Ntot = (long long)P.md.ne * nd;
     const long long i = (long long)w.y + threadIdx.x;
@@ -771,7 +779,11 @@ __global__ void __launch_bounds__(256) apply_batch_kernel(double* u, const doubl
   __shared__ double sh[4];
   const bool err = s->status != 0;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int2 w = items[it];
+    // the item is the same for the whole block: keep it (and everything
+    // derived from it: offsets, pointers, mesh sizes) in scalar registers
+    int2 w = items[it];
+    w.x = __builtin_amdgcn_readfirstlane(w.x);
+    w.y = __builtin_amdgcn_readfirstlane(w.y);
     const SimParams& P = sims[w.x];
     double g = INFINITY;
     for (int q = P.relax_p0 + threadIdx.x; q < P.relax_p1; q += blockDim.x)

@@ -486,9 +486,23 @@ __global__ void __launch_bounds__((RhsShape<DIM, N, T, E>::THREADS))
   __shared__ double sred[S::EN];
   __shared__ int snbr[E * 2 * DIM];
   __shared__ double s_dt;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int2 w = items[it];
+  __shared__ MeshDims smd;
+  // One work item per block, no loop over items: a block-stride loop here let
+  // the compiler hoist the FP64 series constants and argument pointers into
+  // vector registers for the whole loop (+80 VGPRs, half the occupancy).  The
+  // items are sorted large-first, so the dispatcher still balances the
+  // uneven simulations.
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
+    // the item is the same for the whole block: keep it (and everything
+    // derived from it: offsets, pointers, mesh sizes) in scalar registers
+    int2 w = items[it];
+    w.x = __builtin_amdgcn_readfirstlane(w.x);
+    w.y = __builtin_amdgcn_readfirstlane(w.y);
     const SimParams& P = sims[w.x];
+    if (threadIdx.x == 0) smd = P.md;
+    __syncthreads();
     RhsArgs a = a0;
     a.y = a0.y + P.base;
     a.u_old = a0.u_old ? a0.u_old + P.base : nullptr;
@@ -500,7 +514,7 @@ __global__ void __launch_bounds__((RhsShape<DIM, N, T, E>::THREADS))
     a.dt_dev = dt_sims_in ? dt_sims_in + w.x : nullptr;
     a.dt_store = dt_sims ? dt_sims + w.x : nullptr;
     a.elem_base = P.elem_base;
-    rhs_block<DIM, N, T, E>(mp, P.md, a, w.y, sbuf, sbuf, sred, &s_dt, snbr);
+    rhs_block<DIM, N, T, E>(mp, smd, a, w.y, sbuf, sbuf, sred, &s_dt, snbr);
     __syncthreads();
   }
 }
@@ -544,7 +558,9 @@ template <int DIM, int N, typename T, int E>
 static hipError_t batch_one(const MeshParams& mp, const RhsArgs& a, const SimParams* sims,
                             const int2* items, int nitems, double* dt_sims,
                             const double* dt_in, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((rhs_batch_kernel<DIM, N, T, E>), dim3(grid),
+  (void)grid;  // one block per item
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL((rhs_batch_kernel<DIM, N, T, E>), dim3(nitems),
                      dim3(RhsShape<DIM, N, T, E>::THREADS), 0, s, mp, a, sims, items, nitems,
                      dt_sims, dt_in);
   return hipGetLastError();
