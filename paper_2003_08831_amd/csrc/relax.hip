@@ -470,10 +470,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 
 // Batched form over (simulation, first element) items; partial per item.
 template <int DIM, int N>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     relax_batch_kernel(const MeshParams mp, const RelaxArgs a0, const SimParams* __restrict__ sims,
                        const int2* __restrict__ items, int nitems) {
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // one work item per block (no block-stride loop: it made the compiler keep
+  // loop-invariant constants in vector registers)
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
     // the item is the same for the whole block: keep it (and everything
     // derived from it: offsets, pointers, mesh sizes) in scalar registers
     int2 w = items[it];
@@ -709,6 +713,8 @@ int relax_batch_epb(const MeshParams& mp) {
 hipError_t launch_relax_batch(const MeshParams& mp, const RelaxArgs& a, const SimParams* sims,
                               const int2* items, int nitems, int grid, hipStream_t s) {
   if (mp.dim != 2) return hipErrorInvalidValue;
+  if (nitems <= 0) return hipSuccess;
+  grid = nitems;  // one block per item
   switch (mp.n) {
     case 2: hipLaunchKernelGGL((relax_batch_kernel<2, 2>), dim3(grid), dim3(256), 0, s, mp, a, sims, items, nitems); break;
     case 3: hipLaunchKernelGGL((relax_batch_kernel<2, 3>), dim3(grid), dim3(256), 0, s, mp, a, sims, items, nitems); break;
