@@ -28,7 +28,7 @@ struct esrk_ctx {
   double* gamma_k = nullptr;
   int32_t* iters = nullptr;
   double* speed_parts = nullptr;
-  void* theta = nullptr;      // Navier-Stokes: entropy-variable gradients
+  void* theta = nullptr;      // Navier-Stokes: viscous fluxes g_m (dim x nv x N, T precision)
   double* visc = nullptr;     // Navier-Stokes: viscous right-hand side
   double* vdiss = nullptr;    // Navier-Stokes: per-element viscous dissipation
   esrk::RelaxPart* relax_parts = nullptr;
@@ -78,7 +78,7 @@ hipError_t viscous(esrk_ctx* x, const double* y, double* diss, hipStream_t s) {
   if (!(x->cfg.mu > 0.0)) return hipSuccess;
   esrk::NsArgs n;
   n.y = y;
-  n.theta = x->theta;
+  n.flux = x->theta;
   n.visc = x->visc;
   n.diss = diss;
   n.mu = x->cfg.mu;

@@ -120,7 +120,7 @@ hipError_t launch_rhs(const MeshParams& mp, int precision, const RhsArgs& a,
 // BR1 viscous terms: theta (T precision, [dim][nv][N]) and Visc (FP64, [nv][N]).
 struct NsArgs {
   const double* y;
-  void* theta;
+  void* flux;  // viscous fluxes g_m, [m][v][node], T precision
   double* visc;
   double* diss;  // nullable, [ne]
   double mu, kappa, R;

@@ -11,11 +11,15 @@
 //
 // Two kernels, one element per block and one thread per node:
 //   grad_kernel : w at the element's nodes into LDS, w of the face neighbours in
-//                 registers, theta for every node -> theta buffer (T precision);
-//   visc_kernel : g_m at the element's nodes into LDS (from u and theta), g_m of
-//                 the face neighbours in registers, Visc -> visc buffer (FP64) and
-//                 the element's viscous entropy dissipation; in FP32 mode the
-//                 applies D g_m run as one small GEMM per block on the MFMA units.
+//                 registers, theta at every node, then g_m from (u, theta) and
+//                 the element's dissipation; g -> flux buffer (T precision);
+//   visc_kernel : g_m of the element's nodes into LDS, g_m of the face
+//                 neighbours from the buffer, Visc -> visc buffer (FP64); in
+//                 FP32 mode the applies D g_m run as one small GEMM per block on
+//                 the MFMA units.
+// The flux buffer holds g rather than theta: the divergence then reads 5
+// values per neighbour face node instead of recomputing g there from u and
+// all of theta (20 values).
 // The fused stage kernel adds the visc buffer to the inviscid right-hand side.
 #include <type_traits>
 
@@ -206,17 +210,20 @@ __device__ __forceinline__ void viscous_flux(const T* q, const T (*th)[DIM + 2],
 
 template <int DIM, int N, typename T>
 __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
-    grad_kernel(const MeshParams mp, const double* __restrict__ y, T* __restrict__ theta) {
+    grad_kernel(const MeshParams mp, double mu, double kappa, double R,
+                const double* __restrict__ y, T* __restrict__ gflux,
+                double* __restrict__ diss) {
   using G = NsGeo<DIM, N>;
   constexpr int ND = G::ND, NV = G::NV, E = G::E;
   __shared__ T sw[NV * E * ND];
+  __shared__ double sd[E * ND];
   const int tid = threadIdx.x;
   const int e = tid / ND;
   const int i = tid - e * ND;
   const int k = blockIdx.x * E + e;
   const bool valid = e < E && k < mp.ne;
   const long long Ntot = (long long)mp.ne * ND;
-  const T gg = T(mp.gg);
+  const T gg = T(mp.gg), Tmu = T(mu), Tk = T(kappa), TR = T(R);
   int im[3] = {0, 0, 0};
   {
     int ii = i;
@@ -227,9 +234,8 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
     }
   }
   // own node
-  T wo[NV];
+  T q[NV], wo[NV];
   if (valid) {
-    T q[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) q[v] = T(y[v * Ntot + (long long)k * ND + i]);
     entropy_vars<T, DIM>(q, gg, wo);
@@ -252,54 +258,77 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
 #pragma unroll
       for (int q2 = 0; q2 < d; ++q2) stride *= N;
       const int inb = i + (hi_face ? -(N - 1) : (N - 1)) * stride;
-      T q[NV], wn[NV];
+      T qn[NV], wn[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) q[v] = T(y[v * Ntot + (long long)kn * ND + inb]);
-      entropy_vars<T, DIM>(q, gg, wn);
+      for (int v = 0; v < NV; ++v) qn[v] = T(y[v * Ntot + (long long)kn * ND + inb]);
+      entropy_vars<T, DIM>(qn, gg, wn);
       const T sg = hi_face ? T(mp.inv_w_end) : -T(mp.inv_w_end);
 #pragma unroll
       for (int v = 0; v < NV; ++v) lift[d][v] = sg * T(0.5) * (wn[v] - wo[v]);
     }
   }
   __syncthreads();
-  if (!valid) return;
+  double dsum = 0.0;
+  if (valid) {
+    T th[DIM][NV];
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    int stride = 1;
+    for (int d = 0; d < DIM; ++d) {
+      int stride = 1;
 #pragma unroll
-    for (int q2 = 0; q2 < d; ++q2) stride *= N;
-    const int base = i - im[d] * stride;
-    const T metric = T(mp.two_over_h[d]);
+      for (int q2 = 0; q2 < d; ++q2) stride *= N;
+      const int base = i - im[d] * stride;
+      const T metric = T(mp.two_over_h[d]);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      T s = lift[d][v];
+      for (int v = 0; v < NV; ++v) {
+        T s = lift[d][v];
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        // D[i_m][j] = half of the stored 2 D table
-        const T Dij = T(0.5 * mp.D2[im[d] * N + j]);
-        s += Dij * sw[v * E * ND + e * ND + base + j * stride];
+        for (int j = 0; j < N; ++j) {
+          // D[i_m][j] = half of the stored 2 D table
+          const T Dij = T(0.5 * mp.D2[im[d] * N + j]);
+          s += Dij * sw[v * E * ND + e * ND + base + j * stride];
+        }
+        th[d][v] = metric * s;
       }
-      theta[((long long)d * NV + v) * Ntot + (long long)k * ND + i] = metric * s;
+    }
+    const long long gi = (long long)k * ND + i;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      T g[NV];
+      viscous_flux<T, DIM>(q, th, d, gg, TR, Tmu, Tk, g);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        gflux[((long long)d * NV + v) * Ntot + gi] = g[v];
+        dsum += double(th[d][v]) * double(g[v]);
+      }
+    }
+    double M = 1.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) M *= mp.half_h[d] * mp.w[im[d]];
+    dsum *= M;
+  }
+  if (diss) {
+    if (tid < E * ND) sd[tid] = valid ? dsum : 0.0;
+    __syncthreads();
+    if (valid && i == 0) {
+      double s = 0.0;
+      for (int q2 = 0; q2 < ND; ++q2) s += sd[e * ND + q2];
+      diss[k] = s;
     }
   }
 }
 
 template <int DIM, int N, typename T>
 __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
-    visc_kernel(const MeshParams mp, double mu, double kappa, double R,
-                const double* __restrict__ y, const T* __restrict__ theta,
-                double* __restrict__ visc, double* __restrict__ diss) {
+    visc_kernel(const MeshParams mp, const T* __restrict__ gflux, double* __restrict__ visc) {
   using G = NsGeo<DIM, N>;
   constexpr int ND = G::ND, NV = G::NV, E = G::E;
   __shared__ T sg[DIM * NV * E * ND];
-  __shared__ double sd[E * ND];
   const int tid = threadIdx.x;
   const int e = tid / ND;
   const int i = tid - e * ND;
   const int k = blockIdx.x * E + e;
   const bool valid = e < E && k < mp.ne;
   const long long Ntot = (long long)mp.ne * ND;
-  const T gg = T(mp.gg), Tmu = T(mu), Tk = T(kappa), TR = T(R);
   int im[3] = {0, 0, 0};
   {
     int ii = i;
@@ -309,41 +338,22 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
       ii /= N;
     }
   }
-  T go[DIM][NV];
-  double dsum = 0.0;
-  if (valid) {
-    T q[NV], th[DIM][NV];
-    const long long gi = (long long)k * ND + i;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) q[v] = T(y[v * Ntot + gi]);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) th[d][v] = theta[((long long)d * NV + v) * Ntot + gi];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      viscous_flux<T, DIM>(q, th, d, gg, TR, Tmu, Tk, go[d]);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        sg[(d * NV + v) * E * ND + e * ND + i] = go[d][v];
-        dsum += double(th[d][v]) * double(go[d][v]);
-      }
-    }
-    double M = 1.0;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) M *= mp.half_h[d] * mp.w[im[d]];
-    dsum *= M;
-  }
-  if (tid < E * ND) sd[tid] = valid ? dsum : 0.0;
-  // face neighbours' g_d across face d
+  // own g_d into LDS; neighbour g_d across face d: the central lift
   T lift[DIM][NV];
 #pragma unroll
   for (int d = 0; d < DIM; ++d)
 #pragma unroll
     for (int v = 0; v < NV; ++v) lift[d][v] = T(0);
   if (valid) {
+    const long long gi = (long long)k * ND + i;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
+      T go[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        go[v] = gflux[((long long)d * NV + v) * Ntot + gi];
+        sg[(d * NV + v) * E * ND + e * ND + i] = go[v];
+      }
       const bool lo_face = im[d] == 0, hi_face = im[d] == N - 1;
       if (!lo_face && !hi_face) continue;
       const int kn = ns_neighbour<DIM>(mp, k, d, hi_face ? +1 : -1);
@@ -352,17 +362,10 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
       for (int q2 = 0; q2 < d; ++q2) stride *= N;
       const int inb = i + (hi_face ? -(N - 1) : (N - 1)) * stride;
       const long long gn = (long long)kn * ND + inb;
-      T q[NV], th[DIM][NV], gn_d[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) q[v] = T(y[v * Ntot + gn]);
-#pragma unroll
-      for (int d2 = 0; d2 < DIM; ++d2)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) th[d2][v] = theta[((long long)d2 * NV + v) * Ntot + gn];
-      viscous_flux<T, DIM>(q, th, d, gg, TR, Tmu, Tk, gn_d);
       const T sgn = hi_face ? T(mp.inv_w_end) : -T(mp.inv_w_end);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) lift[d][v] = sgn * T(0.5) * (gn_d[v] - go[d][v]);
+      for (int v = 0; v < NV; ++v)
+        lift[d][v] = sgn * T(0.5) * (gflux[((long long)d * NV + v) * Ntot + gn] - go[v]);
     }
   }
   __syncthreads();
@@ -404,23 +407,18 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
       visc[v * Ntot + gi] = acc;
     }
   }
-  if (diss && valid && i == 0) {
-    double s = 0.0;
-    for (int q2 = 0; q2 < ND; ++q2) s += sd[e * ND + q2];
-    diss[k] = s;
-  }
 }
 
 template <int DIM, int N, typename T>
 static hipError_t ns_one(const MeshParams& mp, const NsArgs& a, hipStream_t s) {
   using G = NsGeo<DIM, N>;
   const int blocks = (mp.ne + G::E - 1) / G::E;
-  hipLaunchKernelGGL((grad_kernel<DIM, N, T>), dim3(blocks), dim3(G::THREADS), 0, s, mp, a.y,
-                     (T*)a.theta);
+  hipLaunchKernelGGL((grad_kernel<DIM, N, T>), dim3(blocks), dim3(G::THREADS), 0, s, mp, a.mu,
+                     a.kappa, a.R, a.y, (T*)a.flux, a.diss);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((visc_kernel<DIM, N, T>), dim3(blocks), dim3(G::THREADS), 0, s, mp, a.mu,
-                     a.kappa, a.R, a.y, (const T*)a.theta, a.visc, a.diss);
+  hipLaunchKernelGGL((visc_kernel<DIM, N, T>), dim3(blocks), dim3(G::THREADS), 0, s, mp,
+                     (const T*)a.flux, a.visc);
   return hipGetLastError();
 }
 

@@ -460,10 +460,16 @@ __global__ void __launch_bounds__(256) relax_kernel(const MeshParams mp, const R
 }
 // The same with the register budget of four waves per SIMD (one node per
 // lane: 3-D p=3 fits with a few spilled setup values, so all blocks of a
-// 16^3 mesh are resident at once).
+// 16^3 mesh are resident at once) and of three (two nodes per lane, 3-D p=4).
 template <int DIM, int N, bool NET>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     relax_kernel_w4(const MeshParams mp, const RelaxArgs a) {
+  const MeshDims md = dims_of(mp);
+  relax_block<DIM, N, NET>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB, blockIdx.x, 0);
+}
+template <int DIM, int N, bool NET>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+    relax_kernel_w3(const MeshParams mp, const RelaxArgs a) {
   const MeshDims md = dims_of(mp);
   relax_block<DIM, N, NET>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB, blockIdx.x, 0);
 }
@@ -528,6 +534,9 @@ static hipError_t relax_one(const MeshParams& mp, const RelaxArgs& a, hipStream_
     hipLaunchKernelGGL((relax_kernel<DIM, N, true>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
   else if constexpr (DIM == 3 && C::NPL == 1)
     hipLaunchKernelGGL((relax_kernel_w4<DIM, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, mp,
+                       a);
+  else if constexpr (DIM == 3 && C::NPL == 2)
+    hipLaunchKernelGGL((relax_kernel_w3<DIM, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, mp,
                        a);
   else
     hipLaunchKernelGGL((relax_kernel<DIM, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
