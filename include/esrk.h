@@ -76,7 +76,9 @@ typedef struct {
 
 typedef struct esrk_ctx esrk_ctx;
 
-/* Creates a context: validates cfg, builds the Lobatto SBP tables and
+/* Creates a context: validates cfg (ESRK_EINVAL also when a state array,
+ * (dim+2) * elements * (deg+1)^dim values, would exceed 2^31 - 1 entries:
+ * the kernels index it in 32 bits), builds the Lobatto SBP tables and
  * allocates all device workspace (the only allocation the library makes).
  * Sec. 3.1 (diagonal-norm SBP operators on Lobatto nodes). */
 esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out);
@@ -165,7 +167,8 @@ typedef struct esrk_batch esrk_batch;
 
 /* cfgs[0..nsims): 2-D only (ESRK_ENOTSUP otherwise), Euler (mu = 0); dim,
  * deg, precision, tableau, gas_gamma and lambda_scale must agree (EINVAL);
- * nel, lo, hi and cfl may differ.  Allocates all workspace. */
+ * nel, lo, hi and cfl may differ; each simulation's state must stay below
+ * 2^31 entries (32-bit indexing).  Allocates all workspace. */
 esrk_status esrk_batch_create(const esrk_config* cfgs, int nsims, esrk_batch** out);
 void esrk_batch_destroy(esrk_batch* b);
 int esrk_batch_num_sims(const esrk_batch* b);

@@ -120,7 +120,10 @@ esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
     if (c.nel[m] < 1 || !(c.hi[m] > c.lo[m])) return ESRK_EINVAL;
     ne *= (size_t)c.nel[m];
   }
-  if (ne > (size_t)INT32_MAX) return ESRK_EINVAL;
+  // the kernels index a state array (nv fields of ne * (deg+1)^dim nodes) in 32 bits
+  size_t nd = 1;
+  for (int m = 0; m < c.dim; ++m) nd *= (size_t)(c.deg + 1);
+  if (ne * nd * (size_t)(c.dim + 2) > (size_t)INT32_MAX) return ESRK_EINVAL;
   esrk_ctx* x = new (std::nothrow) esrk_ctx();
   if (!x) return ESRK_ENOMEM;
   x->cfg = c;

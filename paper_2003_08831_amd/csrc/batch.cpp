@@ -169,6 +169,9 @@ esrk_status esrk_batch_create(const esrk_config* cfgs, int nsims, esrk_batch** o
       return ESRK_EINVAL;
     for (int m = 0; m < 2; ++m)
       if (c.nel[m] < 1 || !(c.hi[m] > c.lo[m])) return ESRK_EINVAL;
+    // each simulation's state is indexed in 32 bits by the kernels
+    const size_t nd = (size_t)(c0.deg + 1) * (size_t)(c0.deg + 1);
+    if ((size_t)c.nel[0] * (size_t)c.nel[1] * nd * 4 > (size_t)INT32_MAX) return ESRK_EINVAL;
   }
   esrk_batch* b = new (std::nothrow) esrk_batch();
   if (!b) return ESRK_ENOMEM;

@@ -115,7 +115,7 @@ struct PairMeans {
 };
 // WAVE_UNIFORM: the series length may be chosen per wave (volume pairs, each
 // evaluated once).  Interface fluxes are evaluated by both elements of a face
-// and must not depend on other lanes: they use the per-pair rule only.
+// and must not depend on other lanes: they choose per pair.
 template <typename T, bool WAVE_UNIFORM = false>
 __device__ __forceinline__ PairMeans<T> pair_means(T ra, T rb, T ba, T bb) {
   const T sr = ra + rb, dr = ra - rb;
@@ -128,7 +128,10 @@ __device__ __forceinline__ PairMeans<T> pair_means(T ra, T rb, T ba, T bb) {
   PairMeans<T> m;
   m.p_hat = T(0.5) * sr * rsb;
   // wave-uniform choice of the series length (one ballot, no divergence)
-  if (WAVE_UNIFORM && __all(ur < T(kLnShortCut) && ub < T(kLnShortCut))) {
+  // short series: wave-uniform choice for volume pairs, per-pair choice (a
+  // function of the pair alone, so both elements of a face agree) otherwise
+  const bool short_pair = ur < T(kLnShortCut) && ub < T(kLnShortCut);
+  if (WAVE_UNIFORM ? __all(short_pair) : short_pair) {
     constexpr int K = LnShort<T>::terms;
     m.rho_ln = T(0.5) * sr * inv_atanh_over<T, K>(ur);
     m.inv_beta_ln = T(2) * rsb * atanh_over<T, K>(ub);

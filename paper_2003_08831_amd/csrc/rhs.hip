@@ -156,7 +156,8 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
   constexpr int TH = S::THREADS;
 
   const int tid = threadIdx.x;
-  const long long Ntot = (long long)md.ne * ND;
+  // 32-bit node indices: the library rejects meshes with nv * nodes >= 2^31
+  const int Ntot = md.ne * ND;
   const T gg = T(mp.gg);
   const T half_inv_gm1 = T(0.5) / (gg - T(1));
 
@@ -186,7 +187,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
     const int k = k0 + e;
     T q[NV];
     if (k < md.ne) {
-      const long long gi = (long long)k0 * ND + idx;
+      const int gi = k0 * ND + idx;
 #pragma unroll
       for (int v = 0; v < NV; ++v) q[v] = T(a.y[v * Ntot + gi]);
     } else {
@@ -316,8 +317,8 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       const int kn = snbr[e * 2 * DIM + 2 * m + side];
       const int own = base + (side ? (N - 1) * stride : 0);
       const int nbr = base + (side ? 0 : (N - 1) * stride);
-      const long long gL = side ? (long long)k * ND + own : (long long)kn * ND + nbr;
-      const long long gR = side ? (long long)kn * ND + nbr : (long long)k * ND + own;
+      const int gL = side ? k * ND + own : kn * ND + nbr;
+      const int gR = side ? kn * ND + nbr : k * ND + own;
       T ql[NV], qr[NV], F[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -364,7 +365,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
     }
     const int i = idx - e * ND;
     const int slot = e * NDP + i + i / N;
-    const long long gi = (long long)k0 * ND + idx;
+    const int gi = k0 * ND + idx;
     // global operands of the update first (latency hidden by the work below)
     double uo[NV], yv[NV], dp[NV];
 #pragma unroll
