@@ -46,3 +46,42 @@ def test_create_rejects_empty_mesh_and_null():
     assert esrk.load().esrk_create(None, C.byref(h)) == 1
     assert esrk.load().esrk_rhs_euler(None, None, None, None, None) == 1
     assert esrk.load().esrk_step(None, None, None, 0.0, None, None, None) == 1
+
+
+def test_create_rejects_meshes_beyond_32_bit_indexing():
+    # (dim+2) * ne * (deg+1)^dim = 5 * 700^3 * 8 > 2^31 - 1
+    cfg = esrk.make_config(3, 1, (700, 700, 700), (0, 0, 0), (1, 1, 1))
+    h = C.c_void_p()
+    assert esrk.load().esrk_create(C.byref(cfg), C.byref(h)) == 1
+    assert not h.value
+
+
+def test_batch_create_validation():
+    L = esrk.load()
+    h = C.c_void_p()
+    c2 = esrk.make_config(2, 3, (4, 4), (0, 0), (1, 1))
+    c3 = esrk.make_config(3, 3, (4, 4, 4), (0, 0, 0), (1, 1, 1))
+    arr = (esrk.Config * 1)(c3)
+    assert L.esrk_batch_create(arr, 1, C.byref(h)) == 7  # 3-D: not compiled
+    other = esrk.make_config(2, 4, (4, 4), (0, 0), (1, 1))
+    arr = (esrk.Config * 2)(c2, other)
+    assert L.esrk_batch_create(arr, 2, C.byref(h)) == 1  # mixed degree
+    big = esrk.make_config(2, 3, (20000, 20000), (0, 0), (1, 1))
+    arr = (esrk.Config * 2)(c2, big)
+    assert L.esrk_batch_create(arr, 2, C.byref(h)) == 1  # beyond 32-bit indexing
+    assert L.esrk_batch_create(arr, 0, C.byref(h)) == 1
+    assert not h.value
+
+
+def test_network_entry_point_validation():
+    L = esrk.load()
+    assert L.esrk_mlp_grad_work_size(0) == 0
+    assert L.esrk_mlp_grad_work_size(1) == esrk.MLP_TRAINED + 1
+    assert L.esrk_mlp_grad_work_size(65) == 2 * (esrk.MLP_TRAINED + 1)
+    assert L.esrk_mlp_forward(None, None, 4, None, None) == 1
+    assert L.esrk_mlp_grad(None, None, None, 4, None, None, None, None) == 1
+    assert L.esrk_mlp_adam(None, None, None, None, 1, 1e-3, None) == 1
+    assert L.esrk_mlp_prepare(None, None, None, 4, 1, None, None, None) == 1
+    assert L.esrk_set_step_model(None, None, None) == 1
+    assert L.esrk_local_relaxation_solve_ml(None, None, None, None, 1.0, None, None, None,
+                                            None, None, None, None) == 1
