@@ -89,6 +89,10 @@ def lib():
         L.orc_relax_r.restype = C.c_longdouble
         L.orc_step.argtypes = [mp, C.c_int, C.POINTER(RelaxOpts), C.c_double, C.c_double,
                                dp, dp, dp, dp, dp, C.POINTER(C.c_long)]
+        L.orc_global_relaxation_solve.argtypes = [mp, C.POINTER(RelaxOpts), dp, dp, dp, dp, dp,
+                                                  dp, dp, C.POINTER(C.c_int)]
+        L.orc_global_relax_r.argtypes = [mp, dp, dp, dp, C.c_double, C.POINTER(C.c_int)]
+        L.orc_global_relax_r.restype = C.c_longdouble
         L.orc_mlp_forward.argtypes = [dp, dp, C.c_int, dp]
         L.orc_mlp_grad.argtypes = [dp, dp, dp, C.c_int, dp, dp]
         L.orc_mlp_adam.argtypes = [dp, dp, dp, dp, C.c_int, C.c_double]
@@ -345,3 +349,26 @@ def elem_max_speed(m: Mesh, u):
     s = np.zeros(ne)
     assert lib().orc_elem_max_speed(C.byref(m), _p(np.ascontiguousarray(u)), _p(s)) == 0
     return s
+
+
+def global_relaxation_solve(m: Mesh, u_old, du, deta, opts: RelaxOpts | None = None):
+    """One global gamma (entropy equality); returns dict(gamma, phi0, curv, noise, iters, rc)."""
+    opts = opts or relax_opts()
+    u_old = np.ascontiguousarray(u_old, dtype=np.float64)
+    du = np.ascontiguousarray(du, dtype=np.float64)
+    deta = np.ascontiguousarray(deta, dtype=np.float64)
+    g, p0, cu, no = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    it = C.c_int(0)
+    rc = lib().orc_global_relaxation_solve(C.byref(m), C.byref(opts), _p(u_old), _p(du),
+                                           _p(deta), C.byref(g), C.byref(p0), C.byref(cu),
+                                           C.byref(no), C.byref(it))
+    return dict(gamma=g.value, phi0=p0.value, curv=cu.value, noise=no.value, iters=it.value,
+                rc=rc)
+
+
+def global_relax_r(m: Mesh, u_old, du, deta, gamma):
+    ok = C.c_int(1)
+    r = lib().orc_global_relax_r(C.byref(m), _p(np.ascontiguousarray(u_old)),
+                                 _p(np.ascontiguousarray(du)), _p(np.ascontiguousarray(deta)),
+                                 float(gamma), C.byref(ok))
+    return float(r), bool(ok.value)

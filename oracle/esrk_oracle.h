@@ -111,6 +111,16 @@ int orc_local_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
 long double orc_relax_r(const orc_mesh* g, long k, const double* u_old,
                         const double* du, double deta_k, double gamma, int* admissible);
 
+/* Global relaxation: one gamma with eta(u_old + gamma du) = eta(u_old) + gamma sum_k deta_k
+ * (root of r = sum_k r_k; gamma = 1 if its curvature r(1) - phi(0) is at round-off level,
+ * ORC_ENOROOT if phi(0) >= 0).  phi0, curv, noise, iters nullable. */
+int orc_global_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
+                                const double* u_old, const double* du, const double* deta,
+                                double* gamma, double* phi0, double* curv, double* noise,
+                                int* iters);
+long double orc_global_relax_r(const orc_mesh* g, const double* u_old, const double* du,
+                               const double* deta, double gamma, int* admissible);
+
 /* Generic safeguarded bracket + bisection on a nondecreasing phi with phi(0) = phi0 < 0. */
 typedef long double (*orc_phi_fn)(double gamma, void* ctx, int* admissible);
 int orc_root_nondecreasing(orc_phi_fn phi, void* ctx, double phi0,

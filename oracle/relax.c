@@ -223,3 +223,112 @@ int orc_local_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
   if (gamma) *gamma = isinf(gmin) ? 1.0 : gmin;
   return rc;
 }
+
+/* ---- global relaxation (the relaxation idea applied to the single global
+ * functional eta = sum_k eta_k, Sec. 1; remark after the local theorem) ----
+ * r(gamma) = sum_k r_k(gamma) = eta(u_old + gamma du) - eta(u_old) - gamma sum_k deta_k,
+ * phi = r / gamma; gamma is its positive root (entropy equality). */
+typedef struct {
+  const orc_mesh* g;
+  long N, ne;
+  int nd, nv;
+  const double* u;
+  const double* du;
+  const double* deta;
+  const double* M;
+} glob_ctx;
+
+static long double r_global(const glob_ctx* c, double gamma, int* ok) {
+  long double sum = 0.0L;
+  *ok = 1;
+  for (long k = 0; k < c->ne; ++k) {
+    elem_ctx e = {c->g, k, c->N, c->nd, c->nv, c->u, c->du, c->deta[k], c->M};
+    int okk = 1;
+    long double r = r_of_gamma(&e, gamma, &okk);
+    if (!okk) {
+      *ok = 0;
+      return INFINITY;
+    }
+    sum += r;
+  }
+  return sum;
+}
+
+static long double phi_global(double gamma, void* vctx, int* ok) {
+  long double r = r_global((const glob_ctx*)vctx, gamma, ok);
+  if (!*ok) return INFINITY;
+  return r / (long double)gamma;
+}
+
+int orc_global_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
+                                const double* u_old, const double* du, const double* deta,
+                                double* gamma, double* phi0_out, double* curv_out,
+                                double* noise_out, int* iters_out) {
+  long N = orc_num_nodes(g), ne = orc_num_elems(g);
+  if (N < 0 || !gamma) return ORC_EINVAL;
+  int nd = 1, nv = g->dim + 2;
+  for (int m = 0; m < g->dim; ++m) nd *= g->deg + 1;
+  if (nd > 4096) return ORC_EINVAL;
+  double M[4096];
+  orc__geom_mass(g, M);
+  /* phi(0) = sum_i M_i w(u_old,i).du_i - sum_k deta_k and its round-off scale */
+  long double A = 0.0L, scale = 0.0L, D = 0.0L;
+  for (long k = 0; k < ne; ++k) {
+    for (int i = 0; i < nd; ++i) {
+      long gi = k * nd + i;
+      double ui[5], wi[5];
+      for (int v = 0; v < nv; ++v) ui[v] = u_old[v * N + gi];
+      orc_entropy_vars(g->dim, g->gas_gamma, ui, wi);
+      for (int v = 0; v < nv; ++v) {
+        long double t = (long double)M[i] * wi[v] * du[v * N + gi];
+        A += t;
+        scale += fabsl(t);
+      }
+    }
+    D += deta[k];
+    scale += fabsl((long double)deta[k]);
+  }
+  glob_ctx c = {g, N, ne, nd, nv, u_old, du, deta, M};
+  int ok = 1;
+  double phi0 = (double)(A - D);
+  long double r1 = r_global(&c, 1.0, &ok);
+  double curv = ok ? (double)(r1 - (A - D)) : INFINITY;
+  double noise = (double)(64.0L * DBL_EPSILON * scale);
+  if (phi0_out) *phi0_out = phi0;
+  if (curv_out) *curv_out = curv;
+  if (noise_out) *noise_out = noise;
+  int its = 0;
+  if (curv <= noise) {
+    *gamma = 1.0; /* no curvature above round-off: nothing to relax */
+  } else if (!(phi0 < 0.0)) {
+    *gamma = 0.0;
+    if (iters_out) *iters_out = 0;
+    return ORC_ENOROOT;
+  } else {
+    orc_root_nondecreasing(phi_global, &c, phi0, o, gamma, &its);
+  }
+  if (iters_out) *iters_out = its;
+  return ORC_OK;
+}
+
+/* r(gamma) summed over all elements (for tests). */
+long double orc_global_relax_r(const orc_mesh* g, const double* u_old, const double* du,
+                               const double* deta, double gamma, int* admissible) {
+  double M[4096];
+  orc__geom_mass(g, M);
+  glob_ctx c;
+  c.g = g;
+  c.N = orc_num_nodes(g);
+  c.ne = orc_num_elems(g);
+  c.nv = g->dim + 2;
+  c.nd = 1;
+  for (int m = 0; m < g->dim; ++m) c.nd *= g->deg + 1;
+  c.u = u_old;
+  c.du = du;
+  c.deta = deta;
+  c.M = M;
+  int ok = 1;
+  long double r = r_global(&c, gamma, &ok);
+  if (admissible) *admissible = ok;
+  return r;
+}

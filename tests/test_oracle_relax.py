@@ -226,3 +226,56 @@ def test_vortex_order_with_relaxation_at_relaxed_time(orc):
         e = view(ms, u - I.vortex_state(ms, t))[0]
         errs.append(math.sqrt(((e ** 2) * node_mass(orc, ms)).sum() / 100.0))
     assert math.log(errs[0] / errs[1], 2) > 3.5, errs
+
+
+# ---- global relaxation (one gamma for the total entropy) ----
+
+def test_global_root_brackets_and_lies_between_local_roots(orc):
+    """phi_global = sum_k phi_k is a sum of nondecreasing functions with roots
+    gamma_k, so its root lies in [min_k gamma_k, max_k gamma_k] over the active
+    elements; the returned lower end has r <= 0 and the point one tolerance
+    above it has r >= 0 (a bracket of the root), and r there is the total
+    entropy change minus gamma times the estimate (entropy equality)."""
+    for seed, tab in ((3, orc.SSPRK33), (5, orc.RK44)):
+        ms, m, u = _small_setup(orc, seed=seed)
+        du, deta = orc.rk_step(m, tab, u, orc.cfl_dt(m, u, 0.5))
+        loc = orc.local_relaxation_solve(m, u, du, deta)
+        glob = orc.global_relaxation_solve(m, u, du, deta)
+        assert glob["rc"] == 0 and loc["rc"] == 0
+        g = glob["gamma"]
+        act = np.isfinite(loc["gamma_k"])
+        assert loc["gamma_k"][act].min() - 1e-14 <= g <= loc["gamma_k"][act].max() + 1e-14
+        r_lo, ok = orc.global_relax_r(m, u, du, deta, g)
+        r_hi, ok2 = orc.global_relax_r(m, u, du, deta, g + 2e-15 * max(1.0, g))
+        assert ok and ok2
+        assert r_lo <= glob["noise"] and r_hi >= -glob["noise"]
+        # entropy equality, read through the element entropies
+        eta0 = orc.elem_entropy(m, u).sum()
+        eta1 = orc.elem_entropy(m, u + g * du).sum()
+        sc = np.abs(orc.elem_entropy(m, u)).sum()
+        assert abs(eta1 - eta0 - g * deta.sum()) <= 1e-13 * sc
+
+
+def test_global_equals_local_on_a_single_element(orc):
+    ms = I.MeshSpec(dim=2, deg=4, nel=(1, 1, 1), lo=(0, 0, 0), hi=(1, 1, 1))
+    m = orc_mesh(orc, ms)
+    u = I.random_state(ms, seed=11, smooth=True)
+    du, deta = orc.rk_step(m, orc.RK44, u, orc.cfl_dt(m, u, 0.5))
+    loc = orc.local_relaxation_solve(m, u, du, deta)
+    glob = orc.global_relaxation_solve(m, u, du, deta)
+    assert abs(glob["gamma"] - loc["gamma_k"][0]) <= 2e-15
+
+
+def test_global_free_stream_and_no_root(orc):
+    ms = I.MeshSpec(dim=2, deg=3, nel=(3, 3, 1), lo=(0, 0, 0), hi=(1, 1, 1))
+    m = orc_mesh(orc, ms)
+    u = I.uniform_state(ms, vel=(0.4, 0.2, 0))
+    du, deta = orc.rk_step(m, orc.SSPRK33, u, 0.01)
+    res = orc.global_relaxation_solve(m, u, du, deta)
+    assert res["rc"] == 0 and res["gamma"] == 1.0
+    ms, m, u = _small_setup(orc, seed=8)
+    du, deta = orc.rk_step(m, orc.RK44, u, orc.cfl_dt(m, u, 0.5))
+    res = orc.global_relaxation_solve(m, u, du, deta)
+    bad = deta.copy()
+    bad[0] += res["phi0"] - 1e-3 * abs(res["curv"])  # total phi(0) > 0
+    assert orc.global_relaxation_solve(m, u, du, bad)["rc"] == orc.ENOROOT
