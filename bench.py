@@ -196,6 +196,38 @@ def run_mode(esrk, I, torch, precision, steps, warmup):
                         dt=float(st[1]), t=float(st[2]))
 
 
+def relax_modes_variant(esrk, I, torch, steps=10, warmup=2):
+    """The headline workload (FP64) with each relaxation of esrk_step: none
+    (plain RK(4,4)), local (gamma = min_k gamma_k) and global (one gamma for
+    the total entropy; host-driven bracket passes, one stream sync each)."""
+    ms = I.tgv_mesh(NEL, DEG)
+    cfg = esrk.make_config(ms.dim, ms.deg, ms.nel, ms.lo, ms.hi, gas_gamma=ms.gas_gamma,
+                           precision=esrk.FP64, tableau=esrk.RK44, cfl=0.5)
+    out = {}
+    for name, mode in (("none", esrk.RELAX_NONE), ("local", esrk.RELAX_LOCAL),
+                       ("global", esrk.RELAX_GLOBAL)):
+        ctx = esrk.Context(cfg)
+        ctx.set_relaxation_mode(mode)
+        u = torch.as_tensor(I.tgv_state(ms, MACH)).to("cuda")
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        stats = torch.zeros(6, dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            ctx.step(u, t, 0.0, None, stats)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.step(u, t, 0.0, None, stats)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - w0
+        rc, bad = ctx.sync_status()
+        if rc != 0:
+            raise RuntimeError(f"{name}: device status {esrk.STATUS.get(rc)} at element {bad}")
+        out[name] = {"ms_per_step": round(el * 1e3 / steps, 4),
+                     "gamma_last": float(stats[0].item())}
+        del ctx, u
+    return out
+
+
 def time_stage_kernel(esrk, torch, ctx, u, reps):
     """Average duration of one fused stage-kernel launch (middle RK stage),
     HIP events on the launch stream (the default stream)."""
@@ -311,6 +343,7 @@ def main():
             "ns_tgv_32cubed_p4_fp32_mfma": ns_variant(esrk, I, torch, esrk.FP32_FLUX, 10, 2),
             "kh_batch_256_fp32_graph": batch_variant(esrk, I, torch, 20),
             "learned_guess_ns_tgv": mlp_variant(esrk, I, torch, learn),
+            "relaxation_modes_tgv16_p3_fp64": relax_modes_variant(esrk, I, torch),
         }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(I, a.cpu_steps)

@@ -55,6 +55,8 @@ typedef enum {
 
 enum { ESRK_FP64 = 0, ESRK_FP32_FLUX = 1 };
 enum { ESRK_SSPRK33 = 0, ESRK_RK44 = 1 };
+/* Relaxation applied by esrk_step (esrk_set_relaxation_mode). */
+enum { ESRK_RELAX_LOCAL = 0, ESRK_RELAX_GLOBAL = 1, ESRK_RELAX_NONE = 2 };
 
 typedef struct {
   int dim;             /* 1, 2 or 3 */
@@ -143,9 +145,38 @@ esrk_status esrk_local_relaxation_solve(esrk_ctx* ctx, const double* u_old,
  * double[6] = {gamma, dt, t, number of inactive elements, largest and total
  * number of phi evaluations of the root solves}) are written on the
  * device.  If the device detects an error, u and t are left unchanged and the
- * status is latched.  No host synchronization, no allocation. */
+ * status is latched.  No host synchronization (in the default local
+ * relaxation mode, see esrk_set_relaxation_mode), no allocation. */
 esrk_status esrk_step(esrk_ctx* ctx, double* u, double* t, double dt, double* gamma_k_out,
                       double* stats_out, void* stream);
+
+/* Global relaxation (Sec. 2, the relaxation equation applied to the total
+ * entropy instead of each element's): one gamma with
+ *   eta(u_old + gamma du) = eta(u_old) + gamma sum_k deta_k,
+ * eta being the total entropy sum_k eta_k, solved to root_tol.  The same
+ * activity rule as the local solve, summed over the mesh: gamma = 1 if the
+ * curvature r(1) - phi(0) is at most
+ * 64 eps (sum_i M_i sum_v |w_v du_v| + sum_k |deta_k|); otherwise
+ * phi(0) >= 0 returns ESRK_ENOROOT.  The root lies between the smallest and
+ * the largest per-element root.  The bracket logic runs on the host between
+ * device passes (each pass sweeps the nodes once for four trial values and
+ * synchronizes the stream), so this call blocks; *gamma (device scalar) is
+ * written before it returns, *passes (nullable, host) receives the number of
+ * passes.  ESRK_ENAN if the sums at gamma = 1 are not finite (a state that is
+ * not physical, say); nothing is latched on the device. */
+esrk_status esrk_global_relaxation_solve(esrk_ctx* ctx, const double* u_old,
+                                         const double* du, const double* deta,
+                                         double* gamma, int* passes, void* stream);
+
+/* Relaxation used by esrk_step: ESRK_RELAX_LOCAL (default: gamma = min_k
+ * gamma_k, enqueue-only), ESRK_RELAX_GLOBAL (the root of
+ * esrk_global_relaxation_solve; the step then synchronizes its stream once
+ * per bracket pass, returns a status latched by its stages at once, and
+ * gamma_k_out is not written) or ESRK_RELAX_NONE (the
+ * unrelaxed Runge-Kutta step, gamma = 1).  In the last two modes stats_out
+ * reports zero inactive elements and zero evaluations.  EINVAL for another
+ * mode. */
+esrk_status esrk_set_relaxation_mode(esrk_ctx* ctx, int mode);
 
 /* Synchronizes `ctx`'s work on the stream of its last call, returns and clears
  * the latched device status; *bad_elem (nullable) receives the smallest

@@ -3,6 +3,7 @@
 // of rhs.hip and relax.hip; this file only validates, sizes and launches.
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -36,6 +37,9 @@ struct esrk_ctx {
   DevScalars* scal = nullptr;
   const float* step_model = nullptr;  // network used by esrk_step for first trial points
   float* step_feats = nullptr;        // raw features written by esrk_step (nullable)
+  int relax_mode = ESRK_RELAX_LOCAL;  // relaxation used by esrk_step
+  double* glob_parts = nullptr;       // global relaxation: block partials
+  double* glob_out = nullptr;         // global relaxation: reduced sums
   hipStream_t last = nullptr;
 };
 
@@ -86,6 +90,121 @@ hipError_t viscous(esrk_ctx* x, const double* y, double* diss, hipStream_t s) {
   n.kappa = x->cfg.mu * (x->cfg.gas_gamma * x->cfg.gas_r / (x->cfg.gas_gamma - 1.0)) /
             x->cfg.prandtl;
   return esrk::launch_ns(x->mp, x->cfg.precision, n, s);
+}
+
+// Global relaxation (one gamma with eta(u_old + gamma du) = eta(u_old) +
+// gamma sum_k deta_k): the bracket logic runs here on the host, each pass
+// evaluates kGlobTrials trial values on the device in one sweep over the
+// nodes and reads back the kGlobParts sums (one stream synchronization per
+// pass).  Same rules as the per-element solve: inactive (gamma = 1) when the
+// curvature is at the round-off level, ESRK_ENOROOT when phi(0) >= 0, bracket
+// [0, 1] doubled up to gamma_max, then regula-falsi-centred trial points until
+// the bracket is narrower than root_tol * max(1, gamma); the lower end is
+// returned.
+// With check_latched, a status latched on the device by the kernels before
+// the solve (a non-physical stage state, say) is returned as it is and stays
+// latched.
+esrk_status global_solve(esrk_ctx* x, const double* u_old, const double* du, const double* deta,
+                         double* gamma_host, int* passes_out, bool check_latched,
+                         hipStream_t s) {
+  double o[esrk::kGlobParts];
+  int passes = 0, latched = 0;
+  auto eval = [&](int first, const esrk::GlobTrials& t) -> bool {
+    ++passes;
+    if (esrk::launch_glob_eval(x->mp, u_old, du, deta, first, t, x->glob_parts, x->glob_out,
+                               s) != hipSuccess)
+      return false;
+    if (hipMemcpyAsync(o, x->glob_out, sizeof(o), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return false;
+    if (first && check_latched &&
+        hipMemcpyAsync(&latched, &x->scal->status, sizeof(int), hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
+      return false;
+    return hipStreamSynchronize(s) == hipSuccess;
+  };
+  esrk::GlobTrials t;
+  for (int j = 0; j < esrk::kGlobTrials; ++j) t.g[j] = 1.0;
+  if (!eval(1, t)) return ESRK_EHIP;
+  if (latched != 0) return (esrk_status)latched;
+  if (!std::isfinite(o[0]) || !std::isfinite(o[1]) || !std::isfinite(o[3])) return ESRK_ENAN;
+  const double phi0 = o[0] - o[2];
+  const double noise = 64.0 * DBL_EPSILON * (o[1] + o[3]);
+  const double B1 = o[4];
+  const double tol = x->cfg.root_tol, gmax = x->cfg.gamma_max;
+  if (passes_out) *passes_out = passes;
+  if (std::isfinite(B1) && B1 <= noise) {
+    *gamma_host = 1.0;
+    return ESRK_OK;
+  }
+  if (!(phi0 < 0.0)) return ESRK_ENOROOT;
+  auto phi_at = [&](double g, double Bg) { return std::isfinite(Bg) ? phi0 + Bg / g : INFINITY; };
+  double lo = 0.0, flo = phi0, hi = 1.0, fhi = phi_at(1.0, B1);
+  if (!(fhi > 0.0)) {
+    // expand: 2, 4, 8, ... up to gamma_max
+    lo = 1.0;
+    flo = fhi;
+    bool found = false;
+    while (!found && lo < gmax) {
+      for (int j = 0; j < esrk::kGlobTrials; ++j) t.g[j] = std::fmin(lo * std::ldexp(1.0, j + 1), gmax);
+      if (!eval(0, t)) return ESRK_EHIP;
+      for (int j = 0; j < esrk::kGlobTrials && !found; ++j) {
+        const double f = phi_at(t.g[j], o[4 + j]);
+        if (f > 0.0) {
+          hi = t.g[j];
+          fhi = f;
+          found = true;
+        } else {
+          lo = t.g[j];
+          flo = f;
+        }
+      }
+    }
+    if (!found) {
+      *gamma_host = gmax;
+      if (passes_out) *passes_out = passes;
+      return ESRK_OK;
+    }
+  }
+  double s_prev = NAN;
+  bool halved = true;
+  for (int pass = 0; pass < x->cfg.root_maxit; ++pass) {
+    const double tw = tol * std::fmax(1.0, hi);
+    const double width = hi - lo;
+    if (width <= tw) break;
+    if (halved) {
+      double c = std::isinf(fhi) ? 0.5 * (lo + hi) : lo - flo * width / (fhi - flo);
+      if (!(c == c)) c = 0.5 * (lo + hi);
+      c = std::fmin(std::fmax(c, lo + 0.25 * tw), hi - 0.25 * tw);
+      double w = std::isnan(s_prev) ? 1e-3 * width : 2.0 * std::fabs(c - s_prev);
+      w = std::fmax(w, 0.25 * tw);
+      for (int j = 0; j < esrk::kGlobTrials; ++j) {
+        const double g = c + (j - 0.5 * (esrk::kGlobTrials - 1)) * w;
+        t.g[j] = std::fmin(std::fmax(g, lo + 0.125 * tw), hi - 0.125 * tw);
+      }
+      s_prev = c;
+    } else {
+      // the last pass did not halve the bracket: evenly spaced points
+      for (int j = 0; j < esrk::kGlobTrials; ++j)
+        t.g[j] = lo + (j + 1) * width / (esrk::kGlobTrials + 1);
+    }
+    if (!eval(0, t)) return ESRK_EHIP;
+    for (int j = 0; j < esrk::kGlobTrials; ++j) {
+      const double f = phi_at(t.g[j], o[4 + j]);
+      if (f <= 0.0) {
+        if (t.g[j] > lo) {
+          lo = t.g[j];
+          flo = f;
+        }
+      } else if (t.g[j] < hi) {
+        hi = t.g[j];
+        fhi = f;
+      }
+    }
+    halved = (hi - lo) <= 0.5 * width;
+  }
+  *gamma_host = lo;
+  if (passes_out) *passes_out = passes;
+  return ESRK_OK;
 }
 
 }  // namespace
@@ -175,6 +294,10 @@ esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
   }
   x->n_relax_parts = esrk::relax_blocks(mp);
   ok = ok && hipMalloc(&x->relax_parts, x->n_relax_parts * sizeof(esrk::RelaxPart)) == hipSuccess;
+  ok = ok &&
+       hipMalloc(&x->glob_parts, (size_t)esrk::glob_blocks(mp) * esrk::kGlobParts *
+                                     sizeof(double)) == hipSuccess &&
+       hipMalloc(&x->glob_out, esrk::kGlobParts * sizeof(double)) == hipSuccess;
   if (!ok) {
     esrk_destroy(x);
     return ESRK_ENOMEM;
@@ -204,6 +327,8 @@ void esrk_destroy(esrk_ctx* x) {
   (void)hipFree(x->visc);
   (void)hipFree(x->vdiss);
   (void)hipFree(x->relax_parts);
+  (void)hipFree(x->glob_parts);
+  (void)hipFree(x->glob_out);
   (void)hipFree(x->scal);
   delete x;
 }
@@ -337,19 +462,51 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
     e = esrk::launch_rhs(x->mp, x->cfg.precision, a, s);
     yin = bufs[i & 1];
   }
-  double* gk = gamma_k_out ? gamma_k_out : x->gamma_k;
-  if (e == hipSuccess) {
+  if (e != hipSuccess) return hip_status(e);
+  int nparts = x->n_relax_parts;
+  if (x->relax_mode == ESRK_RELAX_LOCAL) {
+    double* gk = gamma_k_out ? gamma_k_out : x->gamma_k;
     esrk::RelaxArgs r = relax_args(x, u, x->du, x->deta, nullptr, gk, x->iters);
     r.model = x->step_model;
     r.feats = x->step_feats;
     r.dt_dev = &x->scal->dt;
     r.vfeat = x->cfg.mu > 0.0 ? x->vdiss : nullptr;
     e = esrk::launch_relax(x->mp, r, s);
+  } else {
+    double g = INFINITY;  // +inf partial: the update takes gamma = 1
+    if (x->relax_mode == ESRK_RELAX_GLOBAL) {
+      const esrk_status st = global_solve(x, u, x->du, x->deta, &g, nullptr, true, s);
+      if (st != ESRK_OK) return st;
+    }
+    e = esrk::launch_set_part(x->relax_parts, g, s);
+    nparts = 1;
   }
   if (e == hipSuccess)
-    e = esrk::launch_apply(x->mp, u, x->du, t, x->relax_parts, x->n_relax_parts, x->scal,
-                           &x->scal->dt, stats_out, s);
+    e = esrk::launch_apply(x->mp, u, x->du, t, x->relax_parts, nparts, x->scal, &x->scal->dt,
+                           stats_out, s);
   return hip_status(e);
+}
+
+esrk_status esrk_set_relaxation_mode(esrk_ctx* x, int mode) {
+  if (!x || (mode != ESRK_RELAX_LOCAL && mode != ESRK_RELAX_GLOBAL && mode != ESRK_RELAX_NONE))
+    return ESRK_EINVAL;
+  x->relax_mode = mode;
+  return ESRK_OK;
+}
+
+esrk_status esrk_global_relaxation_solve(esrk_ctx* x, const double* u_old, const double* du,
+                                         const double* deta, double* gamma, int* passes,
+                                         void* stream) {
+  if (!x || !u_old || !du || !deta || !gamma) return ESRK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  x->last = s;
+  double g = 1.0;
+  const esrk_status st = global_solve(x, u_old, du, deta, &g, passes, false, s);
+  if (st != ESRK_OK) return st;
+  if (hipMemcpyAsync(gamma, &g, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return ESRK_EHIP;
+  return ESRK_OK;
 }
 
 esrk_status esrk_local_relaxation_solve_ml(esrk_ctx* x, const double* u_old, const double* du,

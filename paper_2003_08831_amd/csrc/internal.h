@@ -148,6 +148,19 @@ struct RelaxArgs {
   int fp32_increments;
 };
 int relax_blocks(const MeshParams& mp);
+
+// global relaxation: trial values per pass and the partial layout
+// [A, scale, sum deta, sum |deta|, B(g_0) .. B(g_{T-1})]
+constexpr int kGlobTrials = 4;
+constexpr int kGlobParts = 4 + kGlobTrials;
+struct GlobTrials {
+  double g[kGlobTrials];
+};
+int glob_blocks(const MeshParams& mp);
+hipError_t launch_glob_eval(const MeshParams& mp, const double* u_old, const double* du,
+                            const double* deta, int first, const GlobTrials& trials,
+                            double* parts, double* out, hipStream_t s);
+hipError_t launch_set_part(RelaxPart* parts, double g, hipStream_t s);
 hipError_t launch_relax(const MeshParams& mp, const RelaxArgs& a, hipStream_t s);
 // gamma = min over partials (1 if all inactive) -> *gamma and scal->gamma
 hipError_t launch_relax_finish(const RelaxPart* parts, int nparts, DevScalars* scal,

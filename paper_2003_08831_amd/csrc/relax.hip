@@ -707,6 +707,197 @@ hipError_t launch_apply(const MeshParams& mp, double* u, const double* du, doubl
   return hipGetLastError();
 }
 
+// ---- global relaxation (one gamma for the total entropy) ----
+// Per node (thread per node over the whole mesh): the contributions to
+//   A = sum M w(u_old).du, its round-off scale sum M |w_v du_v|, sum_k deta_k,
+//   sum_k |deta_k| (first pass only) and B(g_j) = sum M [relative entropy of
+//   u_old + g_j du w.r.t. u_old] for kGlobTrials trial values g_j,
+// summed per block into parts[block][kGlobParts].  The trial values come from
+// the host, which runs the bracket logic between passes.
+template <int DIM, int N>
+__global__ void __launch_bounds__(256) glob_eval_kernel(const MeshParams mp, const double* u_old,
+                                                        const double* du, const double* deta,
+                                                        int first, GlobTrials trials,
+                                                        double* parts) {
+  constexpr int ND = (DIM == 1) ? N : (DIM == 2) ? N * N : N * N * N;
+  constexpr int NV = DIM + 2;
+  const MeshDims md = dims_of(mp);
+  const int Ntot = md.ne * ND;
+  const int gi = blockIdx.x * 256 + threadIdx.x;
+  const bool valid = gi < Ntot;
+  const double gg = mp.gg, gm1 = gg - 1.0, inv_gm1 = 1.0 / gm1;
+  double acc[kGlobParts];
+#pragma unroll
+  for (int q = 0; q < kGlobParts; ++q) acc[q] = 0.0;
+  bool bad[kGlobTrials];
+#pragma unroll
+  for (int j = 0; j < kGlobTrials; ++j) bad[j] = false;
+  if (valid) {
+    const int i = gi % ND;
+    const double rho = u_old[gi], dr = du[gi];
+    double mom[DIM], dm[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      mom[d] = u_old[(1 + d) * Ntot + gi];
+      dm[d] = du[(1 + d) * Ntot + gi];
+    }
+    const double ene = u_old[(NV - 1) * Ntot + gi], dE = du[(NV - 1) * Ntot + gi];
+    const double invrho = rcp_d(rho);
+    double m2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) m2 += mom[d] * mom[d];
+    const double p = gm1 * (ene - 0.5 * m2 * invrho);
+    const double invp = rcp_d(p);
+    const double beta = 0.5 * rho * invp;
+    double M = 1.0;
+    {
+      int ii = i;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int im = ii % N;
+        ii /= N;
+        double wq = mp.w[0];
+#pragma unroll
+        for (int t = 1; t < N; ++t) wq = (im == t) ? mp.w[t] : wq;
+        M *= md.half_h[d] * wq;
+      }
+    }
+    if (first) {
+      const double s_phys = log_d(p) - gg * log_d(rho);
+      const double v2 = m2 * invrho * invrho;
+      double t = ((gg - s_phys) * inv_gm1 - beta * v2) * dr;
+      double sc = fabs(t);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double td = 2.0 * beta * mom[d] * invrho * dm[d];
+        t += td;
+        sc += fabs(td);
+      }
+      const double te = -2.0 * beta * dE;
+      t += te;
+      sc += fabs(te);
+      acc[0] = M * t;
+      acc[1] = M * sc;
+      if (i == 0) {
+        const double de = deta[gi / ND];
+        acc[2] = de;
+        acc[3] = fabs(de);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kGlobTrials; ++j) {
+      const double g = trials.g[j];
+      const double drg = g * dr;
+      const double r1 = rho + drg;
+      double mdm = 0.0, dm2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double dmg = g * dm[d];
+        mdm += mom[d] * dmg;
+        dm2 += dmg * dmg;
+      }
+      const double q = rcp_d(rho * r1);
+      const double dke = (rho * (2.0 * mdm + dm2) - drg * m2) * q;
+      const double dp = gm1 * (g * dE - 0.5 * dke);
+      const double tr = drg * invrho;
+      const double tp = dp * invp;
+      const bool okn = (r1 > 0.0) && (1.0 + tp > 0.0);
+      if (!okn) {
+        bad[j] = true;
+        continue;
+      }
+      const double tz = (tp - tr) * rho * rho * q;
+      double dv2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double dv = (g * dm[d] - drg * mom[d] * invrho) * rho * q;
+        dv2 += dv * dv;
+      }
+      double h, k;
+      rel_terms(tz, tr, false, h, k);
+      acc[4 + j] = M * (r1 * h * inv_gm1 + rho * k + beta * r1 * dv2);
+    }
+  }
+  // block sums in a fixed order (inadmissible trials: +inf)
+  __shared__ double red[256];
+  __shared__ int sbad[kGlobTrials];
+  if (threadIdx.x < kGlobTrials) sbad[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kGlobTrials; ++j)
+    if (bad[j]) sbad[j] = 1;
+  for (int q = 0; q < kGlobParts; ++q) {
+    red[threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double v = red[0];
+      if (q >= 4 && sbad[q - 4]) v = INFINITY;
+      parts[(long long)blockIdx.x * kGlobParts + q] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Sum of the block partials (fixed order) -> out[kGlobParts].
+__global__ void __launch_bounds__(256) glob_reduce_kernel(const double* parts, int nparts,
+                                                          double* out) {
+  __shared__ double red[256];
+  for (int q = 0; q < kGlobParts; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += 256) s += parts[(long long)b * kGlobParts + q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[q] = red[0];
+    __syncthreads();
+  }
+}
+
+// One relaxation partial carrying a given gamma (+inf: relaxation off), for
+// the update kernel's reduction.
+__global__ void set_part_kernel(RelaxPart* parts, double g) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) parts[0] = RelaxPart{g, 0, 0, 0};
+}
+
+int glob_blocks(const MeshParams& mp) { return (mp.ne * mp.nd + 255) / 256; }
+
+hipError_t launch_glob_eval(const MeshParams& mp, const double* u_old, const double* du,
+                            const double* deta, int first, const GlobTrials& trials,
+                            double* parts, double* out, hipStream_t s) {
+  const int blocks = glob_blocks(mp);
+#define ESRK_GE(D, NN)                                                                  \
+  hipLaunchKernelGGL((glob_eval_kernel<D, NN>), dim3(blocks), dim3(256), 0, s, mp, u_old, \
+                     du, deta, first, trials, parts)
+#define ESRK_GD(D)                     \
+  switch (mp.n) {                      \
+    case 2: ESRK_GE(D, 2); break;      \
+    case 3: ESRK_GE(D, 3); break;      \
+    case 4: ESRK_GE(D, 4); break;      \
+    case 5: ESRK_GE(D, 5); break;      \
+    case 6: ESRK_GE(D, 6); break;      \
+    default: return hipErrorInvalidValue; \
+  }
+  if (mp.dim == 1) { ESRK_GD(1) } else if (mp.dim == 2) { ESRK_GD(2) } else { ESRK_GD(3) }
+#undef ESRK_GD
+#undef ESRK_GE
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(glob_reduce_kernel, dim3(1), dim3(256), 0, s, parts, blocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_part(RelaxPart* parts, double g, hipStream_t s) {
+  hipLaunchKernelGGL(set_part_kernel, dim3(1), dim3(64), 0, s, parts, g);
+  return hipGetLastError();
+}
+
 // ---- batched relaxation launch (2-D meshes) ----
 int relax_batch_epb(const MeshParams& mp) {
   switch (mp.n) {

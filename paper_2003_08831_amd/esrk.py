@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "esrk.h")
 FP64, FP32_FLUX = 0, 1
 MLP_TRAINED, MLP_MODEL, MLP_IN = 1281, 1298, 5
 SSPRK33, RK44 = 0, 1
+RELAX_LOCAL, RELAX_GLOBAL, RELAX_NONE = 0, 1, 2
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "EHIP", 3: "ENOMEM", 4: "ENOROOT", 5: "ENONPHYS",
           6: "ENAN", 7: "ENOTSUP"}
@@ -78,6 +79,10 @@ def load():
     L.esrk_local_relaxation_solve.restype = st
     L.esrk_step.argtypes = [vp, vp, vp, dp, vp, vp, vp]
     L.esrk_step.restype = st
+    L.esrk_global_relaxation_solve.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_int), vp]
+    L.esrk_global_relaxation_solve.restype = st
+    L.esrk_set_relaxation_mode.argtypes = [vp, C.c_int]
+    L.esrk_set_relaxation_mode.restype = st
     L.esrk_sync_status.argtypes = [vp, C.POINTER(C.c_int64)]
     L.esrk_sync_status.restype = st
     L.esrk_status_str.argtypes = [st]
@@ -209,6 +214,17 @@ class Context:
             self._h, _ptr(u_old), _ptr(du), _ptr(deta), float(dt), _ptr(visc_rate),
             _ptr(model), _ptr(feats), _ptr(gamma_k), _ptr(gamma), _ptr(iters),
             _stream(stream)), "esrk_local_relaxation_solve_ml")
+
+    def global_relaxation_solve(self, u_old, du, deta, gamma, stream=None):
+        """Blocks until *gamma is written; returns the number of device passes."""
+        passes = C.c_int(0)
+        _check(load().esrk_global_relaxation_solve(
+            self._h, _ptr(u_old), _ptr(du), _ptr(deta), _ptr(gamma), C.byref(passes),
+            _stream(stream)), "esrk_global_relaxation_solve")
+        return passes.value
+
+    def set_relaxation_mode(self, mode):
+        _check(load().esrk_set_relaxation_mode(self._h, int(mode)), "esrk_set_relaxation_mode")
 
     def set_step_model(self, model=None, feats_out=None):
         # the context keeps the raw pointers: hold the tensors while they are set

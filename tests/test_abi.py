@@ -85,3 +85,9 @@ def test_network_entry_point_validation():
     assert L.esrk_set_step_model(None, None, None) == 1
     assert L.esrk_local_relaxation_solve_ml(None, None, None, None, 1.0, None, None, None,
                                             None, None, None, None) == 1
+
+
+def test_global_relaxation_entry_point_validation():
+    L = esrk.load()
+    assert L.esrk_set_relaxation_mode(None, esrk.RELAX_GLOBAL) == 1
+    assert L.esrk_global_relaxation_solve(None, None, None, None, None, None, None) == 1
