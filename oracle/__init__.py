@@ -19,6 +19,8 @@ _LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 SSPRK33 = 0
 RK44 = 1
+BSRK43 = 2
+BSRK85 = 3
 
 ENOROOT = -4
 ENONPHYS = -5
@@ -98,6 +100,16 @@ def lib():
         L.orc_mlp_adam.argtypes = [dp, dp, dp, dp, C.c_int, C.c_double]
         L.orc_mlp_prepare.argtypes = [dp, dp, dp, C.c_int, C.c_int, dp, dp]
         L.orc_elem_max_speed.argtypes = [mp, dp, dp]
+        ip = C.POINTER(C.c_int)
+        L.orc_tableau.argtypes = [C.c_int, dp, dp, dp, dp, ip, ip, ip]
+        L.orc_rk_step_err.argtypes = [mp, C.c_int, dp, C.c_double, dp, dp, dp]
+        L.orc_error_norm.argtypes = [mp, dp, dp, dp, C.c_double, C.c_double]
+        L.orc_error_norm.restype = C.c_double
+        L.orc_adapt_factor.argtypes = [C.c_double, C.c_int, C.c_int]
+        L.orc_adapt_factor.restype = C.c_double
+        L.orc_adaptive_step.argtypes = [mp, C.c_int, C.POINTER(RelaxOpts), C.c_int,
+                                        C.c_double, C.c_double, C.c_double, C.c_double, dp,
+                                        dp, dp, dp, ip, dp, dp]
         _lib = L
     return _lib
 
@@ -249,6 +261,60 @@ def rk_step(m: Mesh, tab, u_old, dt, want_stages=False):
     if want_stages:
         return du, deta, ys, ks, es
     return du, deta
+
+
+def tableau(tab):
+    """dict(A (s x s), b, bhat, c, s, p, q) of a Runge-Kutta method."""
+    A = np.zeros(64)
+    b, bh, c = np.zeros(8), np.zeros(8), np.zeros(8)
+    s, p, q = C.c_int(), C.c_int(), C.c_int()
+    assert lib().orc_tableau(tab, _p(A), _p(b), _p(bh), _p(c), C.byref(s), C.byref(p),
+                             C.byref(q)) == 0
+    n = s.value
+    return dict(A=A.reshape(8, 8)[:n, :n].copy(), b=b[:n].copy(), bhat=bh[:n].copy(),
+                c=c[:n].copy(), s=n, p=p.value, q=q.value)
+
+
+def rk_step_err(m: Mesh, tab, u_old, dt):
+    """(du, deta, err) with err = dt sum_i (b_i - bhat_i) k_i."""
+    ne, N = sizes(m)
+    u_old = np.ascontiguousarray(u_old, dtype=np.float64)
+    du, err, deta = np.zeros_like(u_old), np.zeros_like(u_old), np.zeros(ne)
+    rc = lib().orc_rk_step_err(C.byref(m), tab, _p(u_old), float(dt), _p(du), _p(deta),
+                               _p(err))
+    if rc != 0:
+        raise RuntimeError(f"orc_rk_step_err failed: {rc}")
+    return du, deta, err
+
+
+def error_norm(m: Mesh, u_old, du, err, atol, rtol):
+    return float(lib().orc_error_norm(C.byref(m), _p(np.ascontiguousarray(u_old)),
+                                      _p(np.ascontiguousarray(du)),
+                                      _p(np.ascontiguousarray(err)), atol, rtol))
+
+
+def adapt_factor(err, q, accepted):
+    return float(lib().orc_adapt_factor(float(err), int(q), int(bool(accepted))))
+
+
+RELAX_LOCAL, RELAX_GLOBAL, RELAX_NONE = 0, 1, 2
+
+
+def adaptive_step(m: Mesh, tab, u, t, dt=0.0, mode=RELAX_LOCAL, atol=1e-4, rtol=1e-4,
+                  cfl=0.5, opts: RelaxOpts | None = None):
+    """One error-controlled attempt, in place on u (numpy) if accepted.
+    Returns dict(t, gamma, err, accepted, dt_next, dt, rc)."""
+    opts = opts or relax_opts()
+    assert u.dtype == np.float64 and u.flags["C_CONTIGUOUS"]
+    tt, gam, en, dtn, dtu = (C.c_double(t), C.c_double(1.0), C.c_double(0.0),
+                             C.c_double(0.0), C.c_double(0.0))
+    acc = C.c_int(0)
+    rc = lib().orc_adaptive_step(C.byref(m), tab, C.byref(opts), int(mode), float(atol),
+                                 float(rtol), float(cfl), float(dt), _p(u), C.byref(tt),
+                                 C.byref(gam), C.byref(en), C.byref(acc), C.byref(dtn),
+                                 C.byref(dtu))
+    return dict(t=tt.value, gamma=gam.value, err=en.value, accepted=bool(acc.value),
+                dt_next=dtn.value, dt=dtu.value, rc=rc)
 
 
 def local_relaxation_solve(m: Mesh, u_old, du, deta, opts: RelaxOpts | None = None):

@@ -79,7 +79,13 @@ double orc_cfl_dt(const orc_mesh* g, const double* u, double cfl);
 /* ---- explicit Runge-Kutta step with the entropy estimate (Sec. 2, RK example) ---- */
 #define ORC_SSPRK33 0
 #define ORC_RK44 1
+#define ORC_BSRK43 2 /* Bogacki-Shampine 3(2), embedded pair */
+#define ORC_BSRK85 3 /* Bogacki-Shampine 5(4), embedded pair */
 int orc_tableau_stages(int tableau);
+/* Butcher tableau, zero padded to 8 stages: A[8*8] row-major, b, bhat (zero
+ * without an embedded method), c; s stages, order p, embedded order q (0: none). */
+int orc_tableau(int tableau, double* A, double* b, double* bhat, double* c, int* s, int* p,
+                int* q);
 /* One step from u_old with step dt.  Outputs:
  *   du[nv*N]   = dt * sum_i b_i k_i          (u_new - u_old)
  *   deta[N_e]  = dt * sum_i b_i e_i,k        (eta_new - eta_old)
@@ -90,12 +96,31 @@ int orc_rk_step(const orc_mesh* g, int tableau, const double* u_old, double dt,
                 double* du, double* deta, double* ystages, double* kstages,
                 double* estages);
 
+/* The same step plus the embedded pair's error estimate
+ * err[nv*N] = dt sum_i (b_i - bhat_i) k_i (ORC_EINVAL without an embedded method). */
+int orc_rk_step_err(const orc_mesh* g, int tableau, const double* u_old, double dt,
+                    double* du, double* deta, double* err);
+/* sqrt(mean over all nv*N entries of (err / (atol + rtol max(|u_old|, |u_old+du|)))^2) */
+double orc_error_norm(const orc_mesh* g, const double* u_old, const double* du,
+                      const double* err, double atol, double rtol);
+/* Step-size factor clip(safety err^(-1/(q+1)), 0.1, 10), safety 0.9 after an
+ * accepted step and 0.45 after a rejected one. */
+double orc_adapt_factor(double err, int q, int accepted);
 /* ---- local relaxation (Sec. 2, local relaxation equation and theorem) ---- */
 typedef struct {
   double tol;        /* bracket width at which bisection stops (relative to max(1,gamma)) */
   double gamma_max;  /* largest relaxation parameter tried */
   int maxit;         /* bisection iteration cap */
 } orc_relax_opts;
+
+/* One error-controlled step attempt: the embedded pair's step from u with dt
+ * (dt <= 0: CFL rule), the error norm; accepted iff norm <= 1, then the
+ * relaxation of `mode` (0 local, 1 global, 2 none) and the relaxed update of u
+ * and t; rejected: u and t unchanged.  dt_next = dt * orc_adapt_factor. */
+int orc_adaptive_step(const orc_mesh* g, int tableau, const orc_relax_opts* o, int mode,
+                      double atol, double rtol, double cfl, double dt, double* u, double* t,
+                      double* gamma, double* err, int* accepted, double* dt_next,
+                      double* dt_used);
 
 /* Per element: r_k(gamma) = eta_k(u_old + gamma du) - eta_k(u_old) - gamma deta_k,
  * phi_k = r_k / gamma; gamma_k = its positive root (or +INF for an inactive
