@@ -175,7 +175,7 @@ def run_mode(esrk, I, torch, precision, steps, warmup):
     ctx = esrk.Context(cfg)
     u = torch.as_tensor(I.tgv_state(ms, MACH)).to("cuda")
     t = torch.zeros(1, dtype=torch.float64, device="cuda")
-    stats = torch.zeros(6, dtype=torch.float64, device="cuda")
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
     for _ in range(warmup):
         ctx.step(u, t, 0.0, None, stats)
     torch.cuda.synchronize()
@@ -210,7 +210,7 @@ def relax_modes_variant(esrk, I, torch, steps=10, warmup=2):
         ctx.set_relaxation_mode(mode)
         u = torch.as_tensor(I.tgv_state(ms, MACH)).to("cuda")
         t = torch.zeros(1, dtype=torch.float64, device="cuda")
-        stats = torch.zeros(6, dtype=torch.float64, device="cuda")
+        stats = torch.zeros(8, dtype=torch.float64, device="cuda")
         for _ in range(warmup):
             ctx.step(u, t, 0.0, None, stats)
         torch.cuda.synchronize()

@@ -54,7 +54,12 @@ typedef enum {
 } esrk_status;
 
 enum { ESRK_FP64 = 0, ESRK_FP32_FLUX = 1 };
-enum { ESRK_SSPRK33 = 0, ESRK_RK44 = 1 };
+/* Runge-Kutta methods (Sec. 4 lists the ones used there): SSPRK(3,3);
+ * classical RK(4,4); BSRK(4,3), the Bogacki-Shampine 3(2) embedded pair;
+ * BSRK(8,5), the Bogacki-Shampine 5(4) embedded pair.  The last two evaluate
+ * their last stage at the propagated solution with weight zero: without error
+ * control esrk_step skips that stage. */
+enum { ESRK_SSPRK33 = 0, ESRK_RK44 = 1, ESRK_BSRK43 = 2, ESRK_BSRK85 = 3 };
 /* Relaxation applied by esrk_step (esrk_set_relaxation_mode). */
 enum { ESRK_RELAX_LOCAL = 0, ESRK_RELAX_GLOBAL = 1, ESRK_RELAX_NONE = 2 };
 
@@ -112,7 +117,11 @@ esrk_status esrk_rhs_ns(esrk_ctx* ctx, const double* u, double* dudt, double* et
  *   du  = (stage == 0 ? 0 : du) + dt b_stage k          (u_new - u_old after the last stage)
  *   deta[k] = (stage == 0 ? 0 : deta[k]) + dt b_stage sum_i M_i w(y_in).k
  *   y_out = y^{stage+1} (omitted after the last stage; y_out may be NULL there).
- * For stage 0, y_in must equal u_old.  y_out must not alias y_in or u_old. */
+ * For stage 0, y_in must equal u_old.  y_out must not alias y_in or u_old.
+ * BSRK(4,3) and BSRK(8,5) form y_out from u_old and the slopes of earlier
+ * stages, which the context stores: run the stages of one step in order, with
+ * the same u_old and dt.  They also accumulate the embedded pair's error
+ * estimate in the context (esrk_error_estimate). */
 esrk_status esrk_rk_stage(esrk_ctx* ctx, int stage, double dt, const double* u_old,
                           const double* y_in, double* y_out, double* du, double* deta,
                           void* stream);
@@ -141,10 +150,14 @@ esrk_status esrk_local_relaxation_solve(esrk_ctx* ctx, const double* u_old,
 /* One whole locally relaxed step, in place on u (Sec. 2: RK step, estimate,
  * gamma = min_k gamma_k, u <- u + gamma du, t <- t + gamma dt).  t is a device
  * scalar.  dt > 0 is used as given; dt <= 0 takes dt from the CFL rule on the
- * device.  gamma_k_out (nullable, [num_elems]) and stats_out (nullable, device
- * double[6] = {gamma, dt, t, number of inactive elements, largest and total
- * number of phi evaluations of the root solves}) are written on the
- * device.  If the device detects an error, u and t are left unchanged and the
+ * device, or, under error control (esrk_set_adaptive) after the first
+ * attempt, the controller's proposal.  gamma_k_out (nullable, [num_elems])
+ * and stats_out (nullable, device double[8] = {gamma, dt, t, number of
+ * inactive elements, largest and total number of phi evaluations of the root
+ * solves, weighted error norm (0 without error control), 1 if the attempt was
+ * accepted else 0}) are written on the device.  A rejected attempt leaves u
+ * and t unchanged (gamma_k = +INF, stats gamma = 1) and only shrinks the
+ * proposal.  If the device detects an error, u and t are left unchanged and the
  * status is latched.  No host synchronization (in the default local
  * relaxation mode, see esrk_set_relaxation_mode), no allocation. */
 esrk_status esrk_step(esrk_ctx* ctx, double* u, double* t, double dt, double* gamma_k_out,
@@ -177,6 +190,28 @@ esrk_status esrk_global_relaxation_solve(esrk_ctx* ctx, const double* u_old,
  * reports zero inactive elements and zero evaluations.  EINVAL for another
  * mode. */
 esrk_status esrk_set_relaxation_mode(esrk_ctx* ctx, int mode);
+
+/* Error control of the embedded pairs (Sec. 4 runs them with error-controlled
+ * steps; the controller is not given there, so this is the elementary one):
+ * an attempt with step dt has the estimate err = dt sum_i (b_i - bhat_i) k_i
+ * and the norm
+ *   E = sqrt(mean over all nv*N entries of (err / (atol + rtol max(|u_old|, |u_old + du|)))^2);
+ * it is accepted iff E <= 1, and the next proposal is
+ *   dt * min(10, max(0.1, s E^(-1/(q+1)))), s = 0.9 after an accepted and 0.45
+ * after a rejected attempt (0.1 for a non-finite E, 10 for E = 0), q the
+ * embedded order.  atol = rtol = 0 switches the control off (default);
+ * ESRK_ENOTSUP for a method without an embedded pair, EINVAL for negative or
+ * non-finite tolerances.  Resets the proposal: the next esrk_step with
+ * dt <= 0 starts from the CFL rule again. */
+esrk_status esrk_set_adaptive(esrk_ctx* ctx, double atol, double rtol);
+
+/* The embedded pair's estimate of the last completed run of stages
+ * (esrk_rk_stage or esrk_step): err (nullable, device [nv*N]) receives
+ * dt sum_i (b_i - bhat_i) k_i, *norm (nullable, device scalar) the weighted
+ * norm E of esrk_set_adaptive with the tolerances in effect at the last stage
+ * (EINVAL if none are set).  ESRK_ENOTSUP for a method without an embedded
+ * pair.  Enqueue only. */
+esrk_status esrk_error_estimate(esrk_ctx* ctx, double* err, double* norm, void* stream);
 
 /* Synchronizes `ctx`'s work on the stream of its last call, returns and clears
  * the latched device status; *bad_elem (nullable) receives the smallest

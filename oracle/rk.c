@@ -223,6 +223,7 @@ double orc_adapt_factor(double err, int q, int accepted) {
   /* elementary controller: dt_new = dt * clip(safety * err^(-1/(q+1))) */
   double safety = accepted ? 0.9 : 0.45;
   double f = (err > 0.0) ? safety * pow(err, -1.0 / (q + 1)) : 10.0;
+  if (!(err == err)) f = 0.1; /* no usable estimate: shrink */
   return fmin(10.0, fmax(0.1, f));
 }
 

@@ -19,7 +19,16 @@ struct esrk_ctx {
   esrk_config cfg;
   MeshParams mp;
   int stages;
-  StageCoef sc[4];
+  StageCoef sc[esrk::kMaxStages];
+  esrk::StageRow rows[esrk::kMaxStages];
+  int order_emb = 0;        // embedded order q (0: no embedded method)
+  int nslots = 0;           // stored slopes of a general tableau
+  bool skip_last = false;   // last stage only feeds the error estimate
+  double* kst = nullptr;    // slope store (nslots x nv x N)
+  double* err = nullptr;    // embedded pairs: error estimate (nv x N)
+  double* errk = nullptr;   // embedded pairs: per-element squared weighted errors
+  double atol = 0.0, rtol = 0.0;  // error control (both 0: off)
+  bool have_dt_next = false;      // a proposal from the last controlled attempt exists
   size_t N, ne;
   int nv;
   double* ya = nullptr;
@@ -44,6 +53,89 @@ struct esrk_ctx {
 };
 
 namespace {
+
+// Embedded pairs in Butcher form (A strictly lower triangular, weights b of
+// the propagated solution, bhat of the embedded one), the published
+// Bogacki-Shampine 3(2) and 5(4) methods.  Both evaluate their last stage at
+// the propagated solution with weight zero (b_s = 0).
+struct Pair {
+  int s, q;
+  double A[esrk::kMaxStages][esrk::kMaxStages];
+  double b[esrk::kMaxStages], bh[esrk::kMaxStages];
+};
+
+bool pair_of(int which, Pair* P) {
+  std::memset(P, 0, sizeof(*P));
+  if (which == ESRK_BSRK43) {
+    P->s = 4;
+    P->q = 2;
+    const double a[4][3] = {{0, 0, 0}, {1.0 / 2, 0, 0}, {0, 3.0 / 4, 0},
+                            {2.0 / 9, 1.0 / 3, 4.0 / 9}};
+    const double bh[4] = {7.0 / 24, 1.0 / 4, 1.0 / 3, 1.0 / 8};
+    for (int i = 0; i < 4; ++i) {
+      for (int j = 0; j < i; ++j) P->A[i][j] = a[i][j];
+      P->bh[i] = bh[i];
+    }
+    for (int j = 0; j < 3; ++j) P->b[j] = a[3][j];
+    return true;
+  }
+  if (which == ESRK_BSRK85) {
+    P->s = 8;
+    P->q = 4;
+    const double a[8][7] = {
+        {0, 0, 0, 0, 0, 0, 0},
+        {1.0 / 6, 0, 0, 0, 0, 0, 0},
+        {2.0 / 27, 4.0 / 27, 0, 0, 0, 0, 0},
+        {183.0 / 1372, -162.0 / 343, 1053.0 / 1372, 0, 0, 0, 0},
+        {68.0 / 297, -4.0 / 11, 42.0 / 143, 1960.0 / 3861, 0, 0, 0},
+        {597.0 / 22528, 81.0 / 352, 63099.0 / 585728, 58653.0 / 366080, 4617.0 / 20480, 0, 0},
+        {174197.0 / 959244, -30942.0 / 79937, 8152137.0 / 19744439, 666106.0 / 1039181,
+         -29421.0 / 29068, 482048.0 / 414219, 0},
+        {587.0 / 8064, 0, 4440339.0 / 15491840, 24353.0 / 124800, 387.0 / 44800,
+         2152.0 / 5985, 7267.0 / 94080}};
+    const double bh[8] = {2479.0 / 34992,    0,
+                          123.0 / 416,       612941.0 / 3411720,
+                          43.0 / 1440,       2272.0 / 6561,
+                          79937.0 / 1113912, 3293.0 / 556956};
+    for (int i = 0; i < 8; ++i) {
+      for (int j = 0; j < i; ++j) P->A[i][j] = a[i][j];
+      P->bh[i] = bh[i];
+    }
+    for (int j = 0; j < 7; ++j) P->b[j] = a[7][j];
+    return true;
+  }
+  return false;
+}
+
+// A Butcher tableau in the device's stage form: stage i writes
+//   y_{i+1} = u_old + dt (a_{i+1,i} k_i + sum_{j<i} a_{i+1,j} k_j)
+// with the k_j read back from the slope store; only slopes that a later row
+// (beyond the next stage) uses are stored.  Returns the number of slots.
+int pair_rows(const Pair& P, StageCoef* sc, esrk::StageRow* rows) {
+  int slot_of[esrk::kMaxStages];
+  int nslots = 0;
+  for (int i = 0; i < P.s; ++i) {
+    bool later = false;
+    for (int m = i + 2; m < P.s; ++m) later = later || P.A[m][i] != 0.0;
+    slot_of[i] = later ? nslots++ : -1;
+  }
+  for (int i = 0; i < P.s; ++i) {
+    esrk::StageRow& R = rows[i];
+    std::memset(&R, 0, sizeof(R));
+    R.kstore = slot_of[i] + 1;
+    R.ecoef = P.b[i] - P.bh[i];
+    const bool has_next = i + 1 < P.s;
+    sc[i] = {has_next ? 1.0 : 0.0, 0.0, has_next ? P.A[i + 1][i] : 0.0, P.b[i]};
+    if (has_next)
+      for (int j = 0; j < i; ++j)
+        if (P.A[i + 1][j] != 0.0) {
+          R.prev_slot[R.nprev] = slot_of[j];
+          R.prev_a[R.nprev] = P.A[i + 1][j];
+          ++R.nprev;
+        }
+  }
+  return nslots;
+}
 
 // Runge-Kutta methods in the device's two-register form
 //   y_{i+1} = alpha u_old + beta y_i + c dt k_i,  du += b dt k_i.
@@ -92,6 +184,20 @@ hipError_t viscous(esrk_ctx* x, const double* y, double* diss, hipStream_t s) {
   return esrk::launch_ns(x->mp, x->cfg.precision, n, s);
 }
 
+// The general-tableau and error-estimate part of a stage's arguments.
+void stage_extras(const esrk_ctx* x, int stage, bool last, esrk::RhsArgs& a) {
+  a.kst = x->kst;
+  a.row = x->rows[stage];
+  if (x->order_emb > 0) {
+    a.err = x->err;
+    if (last && (x->atol > 0.0 || x->rtol > 0.0)) {
+      a.errk = x->errk;
+      a.atol = x->atol;
+      a.rtol = x->rtol;
+    }
+  }
+}
+
 // Global relaxation (one gamma with eta(u_old + gamma du) = eta(u_old) +
 // gamma sum_k deta_k): the bracket logic runs here on the host, each pass
 // evaluates kGlobTrials trial values on the device in one sweep over the
@@ -106,9 +212,9 @@ hipError_t viscous(esrk_ctx* x, const double* y, double* diss, hipStream_t s) {
 // latched.
 esrk_status global_solve(esrk_ctx* x, const double* u_old, const double* du, const double* deta,
                          double* gamma_host, int* passes_out, bool check_latched,
-                         hipStream_t s) {
+                         bool check_reject, hipStream_t s) {
   double o[esrk::kGlobParts];
-  int passes = 0, latched = 0;
+  int passes = 0, latched = 0, rejected = 0;
   auto eval = [&](int first, const esrk::GlobTrials& t) -> bool {
     ++passes;
     if (esrk::launch_glob_eval(x->mp, u_old, du, deta, first, t, x->glob_parts, x->glob_out,
@@ -120,12 +226,21 @@ esrk_status global_solve(esrk_ctx* x, const double* u_old, const double* du, con
         hipMemcpyAsync(&latched, &x->scal->status, sizeof(int), hipMemcpyDeviceToHost, s) !=
             hipSuccess)
       return false;
+    if (first && check_reject &&
+        hipMemcpyAsync(&rejected, &x->scal->rejected, sizeof(int), hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
+      return false;
     return hipStreamSynchronize(s) == hipSuccess;
   };
   esrk::GlobTrials t;
   for (int j = 0; j < esrk::kGlobTrials; ++j) t.g[j] = 1.0;
   if (!eval(1, t)) return ESRK_EHIP;
   if (latched != 0) return (esrk_status)latched;
+  if (rejected) {
+    *gamma_host = INFINITY;  // a rejected attempt: the update is skipped anyway
+    if (passes_out) *passes_out = passes;
+    return ESRK_OK;
+  }
   if (!std::isfinite(o[0]) || !std::isfinite(o[1]) || !std::isfinite(o[3])) return ESRK_ENAN;
   const double phi0 = o[0] - o[2];
   const double noise = 64.0 * DBL_EPSILON * (o[1] + o[3]);
@@ -232,7 +347,9 @@ esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
   if (c.dim < 1 || c.dim > 3 || c.deg < 1 || c.deg > esrk::kMaxN - 1) return ESRK_EINVAL;
   if (!(c.gas_gamma > 1.0) || !(c.gas_r > 0.0) || c.mu < 0.0) return ESRK_EINVAL;
   if (c.precision != ESRK_FP64 && c.precision != ESRK_FP32_FLUX) return ESRK_EINVAL;
-  if (c.tableau != ESRK_SSPRK33 && c.tableau != ESRK_RK44) return ESRK_ENOTSUP;
+  if (c.tableau != ESRK_SSPRK33 && c.tableau != ESRK_RK44 && c.tableau != ESRK_BSRK43 &&
+      c.tableau != ESRK_BSRK85)
+    return ESRK_ENOTSUP;
   if (c.mu > 0.0 && !(c.prandtl > 0.0)) return ESRK_EINVAL;
   size_t ne = 1;
   for (int m = 0; m < c.dim; ++m) {
@@ -273,7 +390,16 @@ esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
   mp.lambda_scale = c.lambda_scale;
   mp.cfl = x->cfg.cfl;
   mp.hmin = hmin;
-  x->stages = tableau_coefs(c.tableau, x->sc);
+  for (int i = 0; i < esrk::kMaxStages; ++i) std::memset(&x->rows[i], 0, sizeof(x->rows[i]));
+  Pair P;
+  if (pair_of(c.tableau, &P)) {
+    x->stages = P.s;
+    x->order_emb = P.q;
+    x->nslots = pair_rows(P, x->sc, x->rows);
+    x->skip_last = P.b[P.s - 1] == 0.0;
+  } else {
+    x->stages = tableau_coefs(c.tableau, x->sc);
+  }
   x->ne = ne;
   x->N = ne * (size_t)mp.nd;
   x->nv = c.dim + 2;
@@ -298,6 +424,11 @@ esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
        hipMalloc(&x->glob_parts, (size_t)esrk::glob_blocks(mp) * esrk::kGlobParts *
                                      sizeof(double)) == hipSuccess &&
        hipMalloc(&x->glob_out, esrk::kGlobParts * sizeof(double)) == hipSuccess;
+  if (x->nslots > 0)
+    ok = ok && hipMalloc(&x->kst, (size_t)x->nslots * len * sizeof(double)) == hipSuccess;
+  if (x->order_emb > 0)
+    ok = ok && hipMalloc(&x->err, len * sizeof(double)) == hipSuccess &&
+         hipMalloc(&x->errk, ne * sizeof(double)) == hipSuccess;
   if (!ok) {
     esrk_destroy(x);
     return ESRK_ENOMEM;
@@ -329,6 +460,9 @@ void esrk_destroy(esrk_ctx* x) {
   (void)hipFree(x->relax_parts);
   (void)hipFree(x->glob_parts);
   (void)hipFree(x->glob_out);
+  (void)hipFree(x->kst);
+  (void)hipFree(x->err);
+  (void)hipFree(x->errk);
   (void)hipFree(x->scal);
   delete x;
 }
@@ -392,6 +526,7 @@ esrk_status esrk_rk_stage(esrk_ctx* x, int stage, double dt, const double* u_old
   a.sc = x->sc[stage];
   a.stage_mode = 1;
   a.first = stage == 0;
+  stage_extras(x, stage, last, a);
   return hip_status(esrk::launch_rhs(x->mp, x->cfg.precision, a, s));
 }
 
@@ -434,13 +569,18 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
   if (!x || !u || !t) return ESRK_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   x->last = s;
-  const bool cfl = !(dt > 0.0);
+  const bool adaptive = x->order_emb > 0 && (x->atol > 0.0 || x->rtol > 0.0);
+  // the controller's proposal replaces the CFL rule once there is one
+  const bool proposal = adaptive && !(dt > 0.0) && x->have_dt_next;
+  const bool cfl = !(dt > 0.0) && !proposal;
   hipError_t e = hipSuccess;
   if (cfl) e = esrk::launch_speed(x->mp, u, x->speed_parts, s);
   const double* yin = u;
   double* bufs[2] = {x->ya, x->yb};
-  for (int i = 0; i < x->stages && e == hipSuccess; ++i) {
-    const bool last = i == x->stages - 1;
+  // without error control a last stage of weight zero feeds nothing
+  const int nst = (!adaptive && x->skip_last) ? x->stages - 1 : x->stages;
+  for (int i = 0; i < nst && e == hipSuccess; ++i) {
+    const bool last = i == nst - 1;
     e = viscous(x, yin, x->vdiss, s);
     if (e != hipSuccess) break;
     esrk::RhsArgs a = base_args(x);
@@ -452,6 +592,7 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
     a.eta = x->deta;
     if (i == 0) {
       a.speed_parts = cfl ? x->speed_parts : nullptr;
+      a.dt_dev = proposal ? &x->scal->dt_next : nullptr;
       a.dt_host = dt;
     } else {
       a.dt_dev = &x->scal->dt;
@@ -459,8 +600,18 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
     a.sc = x->sc[i];
     a.stage_mode = 1;
     a.first = i == 0;
+    stage_extras(x, i, last, a);
+    if (!adaptive) {
+      a.err = nullptr;
+      a.errk = nullptr;
+    }
     e = esrk::launch_rhs(x->mp, x->cfg.precision, a, s);
     yin = bufs[i & 1];
+  }
+  if (e == hipSuccess && adaptive) {
+    e = esrk::launch_adapt(x->errk, (int)x->ne, (double)(x->N * x->nv), x->order_emb, 1,
+                           x->scal, nullptr, s);
+    x->have_dt_next = true;
   }
   if (e != hipSuccess) return hip_status(e);
   int nparts = x->n_relax_parts;
@@ -471,11 +622,13 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
     r.feats = x->step_feats;
     r.dt_dev = &x->scal->dt;
     r.vfeat = x->cfg.mu > 0.0 ? x->vdiss : nullptr;
+    r.check_reject = adaptive ? 1 : 0;
     e = esrk::launch_relax(x->mp, r, s);
   } else {
     double g = INFINITY;  // +inf partial: the update takes gamma = 1
     if (x->relax_mode == ESRK_RELAX_GLOBAL) {
-      const esrk_status st = global_solve(x, u, x->du, x->deta, &g, nullptr, true, s);
+      const esrk_status st =
+          global_solve(x, u, x->du, x->deta, &g, nullptr, true, adaptive, s);
       if (st != ESRK_OK) return st;
     }
     e = esrk::launch_set_part(x->relax_parts, g, s);
@@ -483,7 +636,32 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
   }
   if (e == hipSuccess)
     e = esrk::launch_apply(x->mp, u, x->du, t, x->relax_parts, nparts, x->scal, &x->scal->dt,
-                           stats_out, s);
+                           stats_out, adaptive ? 1 : 0, s);
+  return hip_status(e);
+}
+
+esrk_status esrk_set_adaptive(esrk_ctx* x, double atol, double rtol) {
+  if (!x || !(atol >= 0.0) || !(rtol >= 0.0) || std::isinf(atol) || std::isinf(rtol))
+    return ESRK_EINVAL;
+  if ((atol > 0.0 || rtol > 0.0) && x->order_emb == 0) return ESRK_ENOTSUP;
+  x->atol = atol;
+  x->rtol = rtol;
+  x->have_dt_next = false;
+  return ESRK_OK;
+}
+
+esrk_status esrk_error_estimate(esrk_ctx* x, double* err, double* norm, void* stream) {
+  if (!x) return ESRK_EINVAL;
+  if (x->order_emb == 0) return ESRK_ENOTSUP;
+  if (norm && !(x->atol > 0.0 || x->rtol > 0.0)) return ESRK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  x->last = s;
+  hipError_t e = hipSuccess;
+  if (err)
+    e = hipMemcpyAsync(err, x->err, x->N * x->nv * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && norm)
+    e = esrk::launch_adapt(x->errk, (int)x->ne, (double)(x->N * x->nv), x->order_emb, 0,
+                           x->scal, norm, s);
   return hip_status(e);
 }
 
@@ -501,7 +679,7 @@ esrk_status esrk_global_relaxation_solve(esrk_ctx* x, const double* u_old, const
   hipStream_t s = (hipStream_t)stream;
   x->last = s;
   double g = 1.0;
-  const esrk_status st = global_solve(x, u_old, du, deta, &g, passes, false, s);
+  const esrk_status st = global_solve(x, u_old, du, deta, &g, passes, false, false, s);
   if (st != ESRK_OK) return st;
   if (hipMemcpyAsync(gamma, &g, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)

@@ -25,8 +25,10 @@ struct DevScalars {
   double dt;           // step size of the current step
   double gamma;        // global relaxation parameter of the last solve
   int status;          // latched esrk_status (0 = ok)
-  int pad0;
+  int rejected;        // error-controlled step: the last attempt was rejected
   long long bad_elem;  // smallest offending element, or INT64_MAX
+  double err;          // error-controlled step: weighted norm of the estimate
+  double dt_next;      // error-controlled step: proposed next step size
 };
 
 // Per-block partial results (no same-address atomics on the hot path; the
@@ -90,6 +92,19 @@ struct StageCoef {
   double alpha, beta, c, b;
 };
 
+// Rows of a general explicit tableau: y_{i+1} additionally takes
+// dt a_{i+1,j} k_j for the stored slopes of earlier stages j < i.
+constexpr int kMaxPrev = 6;
+constexpr int kMaxStages = 8;
+struct StageRow {
+  int nprev;
+  int prev_slot[kMaxPrev];  // slot of k_j in the slope store
+  double prev_a[kMaxPrev];  // a_{i+1,j}
+  int kstore;               // 1 + slot this stage's slope is stored in (0: not
+                            // stored, so zero-initialized arguments store nothing)
+  double ecoef;             // b_i - bhat_i (embedded pairs)
+};
+
 struct RhsArgs {
   const double* y;      // state the right-hand side is evaluated at
   const double* u_old;  // stage mode: step start state
@@ -107,6 +122,15 @@ struct RhsArgs {
   int stage_mode;       // 0: plain right-hand side, 1: RK stage
   int first;            // stage 0 overwrites du/deta
   DevScalars* scal;
+  // general explicit tableaux (stage mode): slope store, slot j at kst + j nv N
+  double* kst;          // nullable when the tableau needs no stored slopes
+  StageRow row;
+  // embedded pairs (stage mode): err (+)= ecoef dt k, stage 0 overwrites
+  double* err;          // nullable
+  // last stage: per element, sum over nodes and variables of
+  // (err / (atol + rtol max(|u_old|, |u_old + du|)))^2 (nullable)
+  double* errk;
+  double atol, rtol;
 };
 
 // Host tables (Lobatto nodes/weights/derivative matrix), built in extended
@@ -146,6 +170,8 @@ struct RelaxArgs {
   // FP32-flux increments: an element whose phi(0) >= 0 while its entropy
   // change r(1) stays within the FP32 rounding level is inactive, not ENOROOT
   int fp32_increments;
+  // error-controlled steps: nothing to solve when scal->rejected is set
+  int check_reject;
 };
 int relax_blocks(const MeshParams& mp);
 
@@ -171,7 +197,14 @@ hipError_t launch_speed(const MeshParams& mp, const double* u, double* parts, hi
 // when an error is latched); t <- t + gamma dt; optional stats.
 hipError_t launch_apply(const MeshParams& mp, double* u, const double* du, double* t,
                         const RelaxPart* parts, int nparts, DevScalars* scal,
-                        const double* dt_dev, double* stats_out, hipStream_t s);
+                        const double* dt_dev, double* stats_out, int adaptive, hipStream_t s);
+// Error control: err = sqrt(sum_k errk[k] / count) -> scal->err,
+// scal->rejected = !(err <= 1), scal->dt_next = scal->dt * factor(err, q)
+// (the factor clip(safety err^(-1/(q+1)), 0.1, 10), safety 0.9 after an
+// accepted and 0.45 after a rejected attempt; 0.1 for a non-finite err).
+// With decide = 0 only *norm_out (device scalar) receives err.
+hipError_t launch_adapt(const double* errk, int ne, double count, int q, int decide,
+                        DevScalars* scal, double* norm_out, hipStream_t s);
 
 // ---- network kernels ----
 hipError_t launch_mlp_forward(const float* p, const float* X, int B, float* Y, hipStream_t s);

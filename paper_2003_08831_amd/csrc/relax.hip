@@ -171,6 +171,15 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
   const bool valid = k < md.ne;
   const long long Ntot = (long long)md.ne * ND;
   const double gg = mp.gg, gm1 = gg - 1.0, inv_gm1 = 1.0 / gm1;
+  if (a.check_reject && a.scal->rejected) {
+    // a rejected error-controlled attempt: nothing to relax
+    if (valid && sl == 0) {
+      a.gamma_k[k] = INFINITY;
+      if (a.iters) a.iters[k] = 0;
+    }
+    if (threadIdx.x == 0) a.parts[part] = RelaxPart{INFINITY, 0, 0, 0};
+    return;
+  }
 
   // per-node constants along the relaxation line
   double rho[NPL], mom[NPL][DIM], ene[NPL], dr[NPL], dm[NPL][DIM], dE[NPL];
@@ -655,10 +664,12 @@ hipError_t launch_relax_finish(const RelaxPart* parts, int nparts, DevScalars* s
 __global__ void __launch_bounds__(256) apply_kernel(double* u, const double* du, long long len,
                                                     double* t, const RelaxPart* parts,
                                                     int nparts, DevScalars* s,
-                                                    const double* dt_dev, double* stats_out) {
+                                                    const double* dt_dev, double* stats_out,
+                                                    int adaptive) {
   __shared__ double sh[4];
   const double g = reduce_gamma(parts, nparts, sh);
-  const bool err = s->status != 0;
+  const bool rejected = adaptive && s->rejected;
+  const bool err = s->status != 0 || rejected;
   if (!err) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len;
          i += (long long)gridDim.x * blockDim.x)
@@ -691,6 +702,8 @@ __global__ void __launch_bounds__(256) apply_kernel(double* u, const double* du,
         stats_out[3] = inact;
         stats_out[4] = imax;
         stats_out[5] = isum;
+        stats_out[6] = adaptive ? s->err : 0.0;
+        stats_out[7] = rejected ? 0.0 : 1.0;
       }
     }
   }
@@ -698,12 +711,49 @@ __global__ void __launch_bounds__(256) apply_kernel(double* u, const double* du,
 
 hipError_t launch_apply(const MeshParams& mp, double* u, const double* du, double* t,
                         const RelaxPart* parts, int nparts, DevScalars* scal,
-                        const double* dt_dev, double* stats_out, hipStream_t s) {
+                        const double* dt_dev, double* stats_out, int adaptive,
+                        hipStream_t s) {
   const long long len = (long long)(mp.dim + 2) * mp.ne * mp.nd;
   long long blocks = (len + 255) / 256;
   if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(apply_kernel, dim3(blocks), dim3(256), 0, s, u, du, len, t, parts, nparts,
-                     scal, dt_dev, stats_out);
+                     scal, dt_dev, stats_out, adaptive);
+  return hipGetLastError();
+}
+
+// Error control of the embedded pairs: one block sums the per-element
+// squared weighted errors in a fixed order and decides the attempt.
+__global__ void __launch_bounds__(256) adapt_kernel(const double* errk, int ne, double count,
+                                                    int q, int decide, DevScalars* s,
+                                                    double* norm_out) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < ne; k += 256) acc += errk[k];
+  acc = block_sum256(acc, sh);
+  if (threadIdx.x == 0) {
+    const double err = sqrt(acc / count);
+    const bool ok = err <= 1.0;
+    double f;
+    if (!(err == err) || isinf(err))
+      f = 0.1;
+    else if (err > 0.0)
+      f = (ok ? 0.9 : 0.45) * pow(err, -1.0 / (q + 1));
+    else
+      f = 10.0;
+    f = fmin(10.0, fmax(0.1, f));
+    if (norm_out) *norm_out = err;
+    if (decide) {
+      s->err = err;
+      s->rejected = ok ? 0 : 1;
+      s->dt_next = s->dt * f;
+    }
+  }
+}
+
+hipError_t launch_adapt(const double* errk, int ne, double count, int q, int decide,
+                        DevScalars* scal, double* norm_out, hipStream_t s) {
+  hipLaunchKernelGGL(adapt_kernel, dim3(1), dim3(256), 0, s, errk, ne, count, q, decide, scal,
+                     norm_out);
   return hipGetLastError();
 }
 

@@ -354,9 +354,18 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
     if (a.first && k0 == 0 && tid == 0 && a.dt_store) *a.dt_store = dt;
   }
   const bool want_y = a.stage_mode && a.out && a.sc.beta != 0.0;
-  const bool want_uold = a.stage_mode && a.out;
+  const bool want_uold = a.stage_mode && (a.out || a.errk);
   const bool want_du = a.stage_mode && !a.first;
-  for (int idx = tid; idx < EN; idx += TH) {
+  // weighted squared error per node of this thread (last stage of an
+  // error-controlled step), reduced per element after the entropy rates
+  constexpr int ITER = (EN + TH - 1) / TH;
+  double esq[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) esq[it] = 0.0;
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int idx = tid + it * TH;
+    if (idx >= EN) break;
     const int e = idx / ND;
     const int k = k0 + e;
     if (k >= md.ne) {
@@ -421,16 +430,45 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
 
     if (a.stage_mode) {
       const double cdt = a.sc.c * dt, bdt = a.sc.b * dt;
+      const size_t slot_len = (size_t)NV * Ntot;
       if (a.out) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double y = a.sc.alpha * uo[v] + cdt * kv[v];
           if (want_y) y += a.sc.beta * yv[v];
+          // general tableaux: the earlier stored slopes of this row
+#pragma unroll
+          for (int j = 0; j < kMaxPrev; ++j)
+            if (j < a.row.nprev && a.kst)
+              y += (a.row.prev_a[j] * dt) *
+                   a.kst[a.row.prev_slot[j] * slot_len + (size_t)v * Ntot + gi];
           a.out[v * Ntot + gi] = y;
         }
       }
+      if (a.row.kstore > 0 && a.kst) {
+        double* ks = a.kst + (size_t)(a.row.kstore - 1) * slot_len;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) a.du[v * Ntot + gi] = dp[v] + bdt * kv[v];
+        for (int v = 0; v < NV; ++v) ks[(size_t)v * Ntot + gi] = kv[v];
+      }
+      double dn[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        dn[v] = dp[v] + bdt * kv[v];
+        a.du[v * Ntot + gi] = dn[v];
+      }
+      if (a.err) {
+        const double edt = a.row.ecoef * dt;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double ev = (a.first ? 0.0 : a.err[v * Ntot + gi]) + edt * kv[v];
+          a.err[v * Ntot + gi] = ev;
+          if (a.errk) {
+            const double sc = a.atol + a.rtol * fmax(fabs(uo[v]), fabs(uo[v] + dn[v]));
+            const double q = ev / sc;
+            esq[it] += q * q;
+          }
+        }
+      }
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) a.out[v * Ntot + gi] = kv[v];
@@ -447,6 +485,23 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
         a.eta[k] = prev + a.sc.b * dt * s;
       } else {
         a.eta[k] = s;
+      }
+    }
+  }
+  if (a.errk) {
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = tid + it * TH;
+      if (idx < EN) sred[idx] = esq[it];
+    }
+    __syncthreads();
+    if (tid < E) {
+      const int k = k0 + tid;
+      if (k < md.ne) {
+        double s = 0.0;
+        for (int i = 0; i < ND; ++i) s += sred[tid * ND + i];
+        a.errk[k] = s;
       }
     }
   }

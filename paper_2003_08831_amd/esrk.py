@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "esrk.h")
 
 FP64, FP32_FLUX = 0, 1
 MLP_TRAINED, MLP_MODEL, MLP_IN = 1281, 1298, 5
-SSPRK33, RK44 = 0, 1
+SSPRK33, RK44, BSRK43, BSRK85 = 0, 1, 2, 3
 RELAX_LOCAL, RELAX_GLOBAL, RELAX_NONE = 0, 1, 2
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "EHIP", 3: "ENOMEM", 4: "ENOROOT", 5: "ENONPHYS",
@@ -83,6 +83,10 @@ def load():
     L.esrk_global_relaxation_solve.restype = st
     L.esrk_set_relaxation_mode.argtypes = [vp, C.c_int]
     L.esrk_set_relaxation_mode.restype = st
+    L.esrk_set_adaptive.argtypes = [vp, dp, dp]
+    L.esrk_set_adaptive.restype = st
+    L.esrk_error_estimate.argtypes = [vp, vp, vp, vp]
+    L.esrk_error_estimate.restype = st
     L.esrk_sync_status.argtypes = [vp, C.POINTER(C.c_int64)]
     L.esrk_sync_status.restype = st
     L.esrk_status_str.argtypes = [st]
@@ -226,6 +230,13 @@ class Context:
     def set_relaxation_mode(self, mode):
         _check(load().esrk_set_relaxation_mode(self._h, int(mode)), "esrk_set_relaxation_mode")
 
+    def set_adaptive(self, atol, rtol):
+        _check(load().esrk_set_adaptive(self._h, float(atol), float(rtol)), "esrk_set_adaptive")
+
+    def error_estimate(self, err=None, norm=None, stream=None):
+        _check(load().esrk_error_estimate(self._h, _ptr(err), _ptr(norm), _stream(stream)),
+               "esrk_error_estimate")
+
     def set_step_model(self, model=None, feats_out=None):
         # the context keeps the raw pointers: hold the tensors while they are set
         self._step_model_refs = (model, feats_out)
@@ -233,8 +244,8 @@ class Context:
                "esrk_set_step_model")
 
     def step(self, u, t, dt=0.0, gamma_k=None, stats=None, stream=None):
-        if stats is not None and not isinstance(stats, int) and stats.numel() < 6:
-            raise ValueError("stats needs 6 float64 entries")
+        if stats is not None and not isinstance(stats, int) and stats.numel() < 8:
+            raise ValueError("stats needs 8 float64 entries")
         _check(load().esrk_step(self._h, _ptr(u), _ptr(t), float(dt), _ptr(gamma_k),
                                 _ptr(stats), _stream(stream)), "esrk_step")
 

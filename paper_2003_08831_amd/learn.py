@@ -130,7 +130,7 @@ def gain(ctx: esrk.Context, u: torch.Tensor, t: torch.Tensor, nsteps: int, model
     s = 3 if ctx.cfg.tableau == esrk.SSPRK33 else 4
     ns = ctx.cfg.mu > 0.0
     if dt is None:
-        stats = torch.zeros(6, dtype=torch.float64, device=dev)
+        stats = torch.zeros(8, dtype=torch.float64, device=dev)
         probe = u.clone()
         tp = t.clone()
         ctx.step(probe, tp, 0.0, None, stats, stream=st)

@@ -70,6 +70,9 @@ def test_batch_create_validation():
     arr = (esrk.Config * 2)(c2, big)
     assert L.esrk_batch_create(arr, 2, C.byref(h)) == 1  # beyond 32-bit indexing
     assert L.esrk_batch_create(arr, 0, C.byref(h)) == 1
+    emb = esrk.make_config(2, 3, (4, 4), (0, 0), (1, 1), tableau=esrk.BSRK43)
+    arr = (esrk.Config * 1)(emb)
+    assert L.esrk_batch_create(arr, 1, C.byref(h)) == 7  # embedded pairs: single meshes only
     assert not h.value
 
 
@@ -91,3 +94,9 @@ def test_global_relaxation_entry_point_validation():
     L = esrk.load()
     assert L.esrk_set_relaxation_mode(None, esrk.RELAX_GLOBAL) == 1
     assert L.esrk_global_relaxation_solve(None, None, None, None, None, None, None) == 1
+
+
+def test_error_control_entry_point_validation():
+    L = esrk.load()
+    assert L.esrk_set_adaptive(None, 1e-4, 1e-4) == 1
+    assert L.esrk_error_estimate(None, None, None, None) == 1

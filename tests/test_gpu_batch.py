@@ -50,7 +50,7 @@ def test_batch_step_equals_single_steps(precision, tableau):
         ctx = esrk.Context(cfgs[s])
         us = torch.as_tensor(states[s], device="cuda").clone()
         ts = torch.zeros(1, dtype=torch.float64, device="cuda")
-        st = torch.zeros(6, dtype=torch.float64, device="cuda")
+        st = torch.zeros(8, dtype=torch.float64, device="cuda")
         singles.append((ctx, us, ts, st))
     for step in range(3):
         b.step(u, t, g)

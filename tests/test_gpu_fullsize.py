@@ -50,7 +50,7 @@ def test_vortex_8x8_p3_all_100_steps():
     ms = I.vortex_mesh(8, 3)
     m = orc_mesh(O, ms)
     ctx = ctx_for(ms, tableau=esrk.SSPRK33, cfl=0.5)
-    stats = zeros(6)
+    stats = zeros(8)
     u, t = I.vortex_state(ms), 0.0
     for step in range(100):
         u, t = _check_step(ctx, ms, m, O.SSPRK33, u, t, 0.5, stats, step)
@@ -113,7 +113,7 @@ def _fp32_checks(c32, ms, u, ref, M, S, steps):
     size = (np.abs(U0) * M).sum(axis=(1, 2))
     # momentum components share one scale (the TGV's z-momentum is zero)
     size[1:1 + ms.dim] = size[1:1 + ms.dim].sum()
-    t, stats = zeros(1), zeros(6)
+    t, stats = zeros(1), zeros(8)
     for _ in range(steps):
         c32.step(ud, t, 0.0, None, stats)
     assert c32.sync_status()[0] == 0
@@ -124,7 +124,7 @@ def _fp32_checks(c32, ms, u, ref, M, S, steps):
 def test_tgv16_p3_two_steps(tgv16):
     ms, m, u, _, _ = tgv16
     ctx = ctx_for(ms, tableau=esrk.RK44, cfl=0.5)
-    stats = zeros(6)
+    stats = zeros(8)
     t = 0.0
     for step in range(2):
         u, t = _check_step(ctx, ms, m, O.RK44, u, t, 0.5, stats, step)
@@ -134,7 +134,7 @@ def test_tgv16_p3_two_steps(tgv16):
 def test_tgv16_p3_50_free_steps_conservation_and_entropy(tgv16):
     ms, m, u0, _, _ = tgv16
     ctx = ctx_for(ms, tableau=esrk.RK44, cfl=0.5)
-    ud, t, stats = dev(u0), zeros(1), zeros(6)
+    ud, t, stats = dev(u0), zeros(1), zeros(8)
     M = node_mass(O, ms)
     cons0 = (view(ms, u0) * M).sum(axis=(1, 2))
     sc = (np.abs(view(ms, u0)) * M).sum(axis=(1, 2))

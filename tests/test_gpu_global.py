@@ -89,7 +89,7 @@ def test_step_modes_parity(tab, name, ms, kind):
     cfl = 0.5
     m = orc_mesh(O, ms)
     ctx = ctx_for(ms, tableau=tab, cfl=cfl)
-    stats = zeros(6)
+    stats = zeros(8)
     for mode in (esrk.RELAX_GLOBAL, esrk.RELAX_NONE, esrk.RELAX_LOCAL):
         ctx.set_relaxation_mode(mode)
         u = make_state(ms, kind, seed=9)
@@ -146,7 +146,7 @@ def test_entropy_trajectory_none_local_global():
                        ("global", esrk.RELAX_GLOBAL)):
         ctx = ctx_for(ms, lambda_scale=0.0, cfl=0.5)
         ctx.set_relaxation_mode(mode)
-        ud, t, stats = dev(u0), zeros(1), zeros(6)
+        ud, t, stats = dev(u0), zeros(1), zeros(8)
         etas = []
         for _ in range(40):
             ctx.step(ud, t, 0.0, None, stats)

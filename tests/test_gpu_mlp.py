@@ -194,7 +194,7 @@ def test_step_with_model_equals_plain_step():
     ctx = ctx_for(ms)
     a, b = dev(u), dev(u)
     ta, tb = zeros(1), zeros(1)
-    sa, sb = zeros(6), zeros(6)
+    sa, sb = zeros(8), zeros(8)
     feats = torch.full((ctx.ne * 5,), float("nan"), dtype=F32, device="cuda")
     p = rand_model(31).astype(np.float32)
     p[1281:1298] = 1.0

@@ -101,7 +101,7 @@ def test_ns_stage_chain_and_step_parity(tab, name, ms, kind):
     ref = O.local_relaxation_solve(m, u, du_ref, deta_ref)
     assert ref["rc"] == 0
     t = zeros(1)
-    stats = zeros(6)
+    stats = zeros(8)
     ctx.step(ud, t, dt, None, stats)
     g = host(stats)[0]
     fin = np.isfinite(ref["gamma_k"])

@@ -210,7 +210,7 @@ def test_step_parity(tab, name, ms, kind):
     u = make_state(ms, kind, seed=4)
     m = orc_mesh(O, ms)
     ctx = ctx_for(ms, tableau=tab, cfl=cfl)
-    stats = zeros(6)
+    stats = zeros(8)
     gk = zeros(ctx.ne)
     t_ref = 0.0
     for step in range(5):
@@ -244,7 +244,7 @@ def test_gpu_trajectory_entropy_inequality_and_conservation(name, ms, kind):
     ctx = ctx_for(ms, tableau=tab)
     ud = dev(u0)
     t = zeros(1)
-    stats = zeros(6)
+    stats = zeros(8)
     M = node_mass(O, ms)
     cons0 = (view(ms, u0) * M).sum(axis=(1, 2))
     s = O.tableau_stages(tab)
