@@ -102,6 +102,12 @@ def lib():
         L.orc_elem_max_speed.argtypes = [mp, dp, dp]
         ip = C.POINTER(C.c_int)
         L.orc_tableau.argtypes = [C.c_int, dp, dp, dp, dp, ip, ip, ip]
+        L.orc_rk_step_a.argtypes = [mp, C.c_int, dp, C.c_double, dp, dp, dp]
+        L.orc_local_relaxation_solve_a.argtypes = [
+            mp, C.POINTER(RelaxOpts), dp, dp, dp, dp, dp, dp, dp, dp, dp, ip,
+            C.POINTER(C.c_long)]
+        L.orc_global_relaxation_solve_a.argtypes = [mp, C.POINTER(RelaxOpts), dp, dp, dp, dp,
+                                                    dp, dp, dp, dp, ip]
         L.orc_rk_step_err.argtypes = [mp, C.c_int, dp, C.c_double, dp, dp, dp]
         L.orc_error_norm.argtypes = [mp, dp, dp, dp, C.c_double, C.c_double]
         L.orc_error_norm.restype = C.c_double
@@ -275,6 +281,17 @@ def tableau(tab):
                 c=c[:n].copy(), s=n, p=p.value, q=q.value)
 
 
+def rk_step_a(m: Mesh, tab, u_old, dt):
+    """(du, deta, a) with a_k = phi_k(0) from the stage-wise identity."""
+    ne, N = sizes(m)
+    u_old = np.ascontiguousarray(u_old, dtype=np.float64)
+    du, deta, a = np.zeros_like(u_old), np.zeros(ne), np.zeros(ne)
+    rc = lib().orc_rk_step_a(C.byref(m), tab, _p(u_old), float(dt), _p(du), _p(deta), _p(a))
+    if rc != 0:
+        raise RuntimeError(f"orc_rk_step_a failed: {rc}")
+    return du, deta, a
+
+
 def rk_step_err(m: Mesh, tab, u_old, dt):
     """(du, deta, err) with err = dt sum_i (b_i - bhat_i) k_i."""
     ne, N = sizes(m)
@@ -317,8 +334,9 @@ def adaptive_step(m: Mesh, tab, u, t, dt=0.0, mode=RELAX_LOCAL, atol=1e-4, rtol=
                 dt_next=dtn.value, dt=dtu.value, rc=rc)
 
 
-def local_relaxation_solve(m: Mesh, u_old, du, deta, opts: RelaxOpts | None = None):
-    """Returns dict(gamma, gamma_k, phi0, curv, noise, iters, rc, bad_elem)."""
+def local_relaxation_solve(m: Mesh, u_old, du, deta, opts: RelaxOpts | None = None, a=None):
+    """Returns dict(gamma, gamma_k, phi0, curv, noise, iters, rc, bad_elem);
+    a (optional, [ne]) supplies phi_k(0)."""
     ne, N = sizes(m)
     opts = opts or relax_opts()
     u_old = np.ascontiguousarray(u_old, dtype=np.float64)
@@ -331,8 +349,9 @@ def local_relaxation_solve(m: Mesh, u_old, du, deta, opts: RelaxOpts | None = No
     iters = np.zeros(ne, dtype=np.int32)
     gam = C.c_double(0.0)
     bad = C.c_long(-1)
-    rc = lib().orc_local_relaxation_solve(
-        C.byref(m), C.byref(opts), _p(u_old), _p(du), _p(deta), _p(gk), C.byref(gam),
+    a = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+    rc = lib().orc_local_relaxation_solve_a(
+        C.byref(m), C.byref(opts), _p(u_old), _p(du), _p(deta), _p(a), _p(gk), C.byref(gam),
         _p(phi0), _p(curv), _p(noise), iters.ctypes.data_as(C.POINTER(C.c_int)),
         C.byref(bad))
     return dict(gamma=gam.value, gamma_k=gk, phi0=phi0, curv=curv, noise=noise,
@@ -417,7 +436,7 @@ def elem_max_speed(m: Mesh, u):
     return s
 
 
-def global_relaxation_solve(m: Mesh, u_old, du, deta, opts: RelaxOpts | None = None):
+def global_relaxation_solve(m: Mesh, u_old, du, deta, opts: RelaxOpts | None = None, a=None):
     """One global gamma (entropy equality); returns dict(gamma, phi0, curv, noise, iters, rc)."""
     opts = opts or relax_opts()
     u_old = np.ascontiguousarray(u_old, dtype=np.float64)
@@ -425,9 +444,10 @@ def global_relaxation_solve(m: Mesh, u_old, du, deta, opts: RelaxOpts | None = N
     deta = np.ascontiguousarray(deta, dtype=np.float64)
     g, p0, cu, no = C.c_double(), C.c_double(), C.c_double(), C.c_double()
     it = C.c_int(0)
-    rc = lib().orc_global_relaxation_solve(C.byref(m), C.byref(opts), _p(u_old), _p(du),
-                                           _p(deta), C.byref(g), C.byref(p0), C.byref(cu),
-                                           C.byref(no), C.byref(it))
+    a = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+    rc = lib().orc_global_relaxation_solve_a(C.byref(m), C.byref(opts), _p(u_old), _p(du),
+                                             _p(deta), _p(a), C.byref(g), C.byref(p0),
+                                             C.byref(cu), C.byref(no), C.byref(it))
     return dict(gamma=g.value, phi0=p0.value, curv=cu.value, noise=no.value, iters=it.value,
                 rc=rc)
 

@@ -96,6 +96,11 @@ int orc_rk_step(const orc_mesh* g, int tableau, const double* u_old, double dt,
                 double* du, double* deta, double* ystages, double* kstages,
                 double* estages);
 
+/* The same step plus a[N_e]: phi_k(0) = sum_i M w(u_old).du - deta_k evaluated
+ * as dt sum_i b_i sum_nodes M (w(u_old) - w(y^i)).k_i (the same quantity
+ * without the cancelling difference; entropy variables in extended precision). */
+int orc_rk_step_a(const orc_mesh* g, int tableau, const double* u_old, double dt,
+                  double* du, double* deta, double* a);
 /* The same step plus the embedded pair's error estimate
  * err[nv*N] = dt sum_i (b_i - bhat_i) k_i (ORC_EINVAL without an embedded method). */
 int orc_rk_step_err(const orc_mesh* g, int tableau, const double* u_old, double dt,
@@ -115,7 +120,8 @@ typedef struct {
 
 /* One error-controlled step attempt: the embedded pair's step from u with dt
  * (dt <= 0: CFL rule), the error norm; accepted iff norm <= 1, then the
- * relaxation of `mode` (0 local, 1 global, 2 none) and the relaxed update of u
+ * relaxation of `mode` (0 local, 1 global, 2 none; phi(0) from
+ * orc_rk_step_a) and the relaxed update of u
  * and t; rejected: u and t unchanged.  dt_next = dt * orc_adapt_factor. */
 int orc_adaptive_step(const orc_mesh* g, int tableau, const orc_relax_opts* o, int mode,
                       double atol, double rtol, double cfl, double dt, double* u, double* t,
@@ -132,6 +138,14 @@ int orc_local_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
                                const double* deta, double* gamma_k, double* gamma,
                                double* phi0, double* curv, double* noise,
                                int* iters, long* bad_elem);
+/* The same with phi_k(0) supplied (a[N_e], e.g. from orc_rk_step_a; NULL:
+ * A - deta): phi_k(gamma) = a_k + B_k(gamma)/gamma with B_k the relative
+ * entropy sum; the activity test and its outputs are unchanged. */
+int orc_local_relaxation_solve_a(const orc_mesh* g, const orc_relax_opts* o,
+                                 const double* u_old, const double* du, const double* deta,
+                                 const double* a, double* gamma_k, double* gamma,
+                                 double* phi0, double* curv, double* noise, int* iters,
+                                 long* bad_elem);
 /* r_k(gamma) for one element (for tests). */
 long double orc_relax_r(const orc_mesh* g, long k, const double* u_old,
                         const double* du, double deta_k, double gamma, int* admissible);
@@ -143,6 +157,11 @@ int orc_global_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
                                 const double* u_old, const double* du, const double* deta,
                                 double* gamma, double* phi0, double* curv, double* noise,
                                 int* iters);
+/* The same with the per-element phi_k(0) supplied (summed; NULL: A - D). */
+int orc_global_relaxation_solve_a(const orc_mesh* g, const orc_relax_opts* o,
+                                  const double* u_old, const double* du, const double* deta,
+                                  const double* a, double* gamma, double* phi0, double* curv,
+                                  double* noise, int* iters);
 long double orc_global_relax_r(const orc_mesh* g, const double* u_old, const double* du,
                                const double* deta, double gamma, int* admissible);
 
@@ -151,7 +170,8 @@ typedef long double (*orc_phi_fn)(double gamma, void* ctx, int* admissible);
 int orc_root_nondecreasing(orc_phi_fn phi, void* ctx, double phi0,
                            const orc_relax_opts* o, double* root, int* iters);
 
-/* Whole step: RK step, local relaxation, global gamma, relaxed update.
+/* Whole step: RK step (with phi_k(0) from orc_rk_step_a), local relaxation,
+ * global gamma, relaxed update.
  * dt <= 0 takes dt from the CFL rule.  On return u holds u_gamma, *t the
  * relaxed time t_old + gamma*dt.  gamma_k (nullable, N_e). */
 int orc_step(const orc_mesh* g, int tableau, const orc_relax_opts* o, double cfl,

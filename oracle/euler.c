@@ -94,3 +94,14 @@ double orc_wave_speed(int dim, double gg, const double* u) {
   for (int k = 0; k < dim; ++k) s += fabs(v[k]) + c;
   return s;
 }
+
+/* w = dS/du as above, in extended precision from a double state (internal). */
+void orc__entropy_vars_ld(int dim, double gg, const double* q, long double* w) {
+  long double G = gg, rho = q[0], E = q[dim + 1], m2 = 0.0L;
+  for (int d = 0; d < dim; ++d) m2 += (long double)q[1 + d] * q[1 + d];
+  long double p = (G - 1.0L) * (E - 0.5L * m2 / rho);
+  long double s = logl(p) - G * logl(rho);
+  w[0] = (G - s) / (G - 1.0L) - 0.5L * m2 / (rho * p);
+  for (int d = 0; d < dim; ++d) w[1 + d] = (long double)q[1 + d] / p;
+  w[dim + 1] = -rho / p;
+}

@@ -77,6 +77,7 @@ typedef struct {
   const double* du;
   double deta;
   const double* M;
+  long double shift; /* phi(0) given - (A - deta): 0 unless phi(0) is supplied */
 } elem_ctx;
 
 static long double r_of_gamma(const elem_ctx* c, double gamma, int* ok) {
@@ -104,8 +105,10 @@ static long double phi_elem(double gamma, void* vctx, int* ok) {
   const elem_ctx* c = (const elem_ctx*)vctx;
   long double r = r_of_gamma(c, gamma, ok);
   if (!*ok) return INFINITY;
-  return r / (long double)gamma;
+  return r / (long double)gamma + c->shift;
 }
+
+void orc__entropy_vars_ld(int dim, double gg, const double* q, long double* w);
 
 int orc_root_nondecreasing(orc_phi_fn phi, void* ctx, double phi0,
                            const orc_relax_opts* o, double* root, int* iters) {
@@ -158,6 +161,7 @@ long double orc_relax_r(const orc_mesh* g, long k, const double* u_old, const do
   c.du = du;
   c.deta = deta_k;
   c.M = M;
+  c.shift = 0.0L;
   int ok = 1;
   long double r = r_of_gamma(&c, gamma, &ok);
   if (admissible) *admissible = ok;
@@ -169,6 +173,15 @@ int orc_local_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
                                const double* deta, double* gamma_k, double* gamma,
                                double* phi0_out, double* curv_out, double* noise_out,
                                int* iters_out, long* bad_elem) {
+  return orc_local_relaxation_solve_a(g, o, u_old, du, deta, NULL, gamma_k, gamma, phi0_out,
+                                      curv_out, noise_out, iters_out, bad_elem);
+}
+
+int orc_local_relaxation_solve_a(const orc_mesh* g, const orc_relax_opts* o,
+                                 const double* u_old, const double* du, const double* deta,
+                                 const double* a_in, double* gamma_k, double* gamma,
+                                 double* phi0_out, double* curv_out, double* noise_out,
+                                 int* iters_out, long* bad_elem) {
   long N = orc_num_nodes(g), ne = orc_num_elems(g);
   if (N < 0) return ORC_EINVAL;
   int nd = 1, nv = g->dim + 2;
@@ -184,9 +197,10 @@ int orc_local_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
     long double A = 0.0L, scale = 0.0L;
     for (int i = 0; i < nd; ++i) {
       long gi = k * nd + i;
-      double ui[5], wi[5];
+      double ui[5];
+      long double wi[5];
       for (int v = 0; v < nv; ++v) ui[v] = u_old[v * N + gi];
-      orc_entropy_vars(g->dim, g->gas_gamma, ui, wi);
+      orc__entropy_vars_ld(g->dim, g->gas_gamma, ui, wi);
       for (int v = 0; v < nv; ++v) {
         long double t = (long double)M[i] * wi[v] * du[v * N + gi];
         A += t;
@@ -194,11 +208,15 @@ int orc_local_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
       }
     }
     scale += fabsl((long double)deta[k]);
-    double phi0 = (double)(A - (long double)deta[k]);
-    elem_ctx c = {g, k, N, nd, nv, u_old, du, deta[k], M};
+    /* phi(0) = A - deta, or the supplied value of the same quantity */
+    long double naive = A - (long double)deta[k];
+    long double a = a_in ? (long double)a_in[k] : naive;
+    double phi0 = (double)a;
+    elem_ctx c = {g, k, N, nd, nv, u_old, du, deta[k], M, a - naive};
     int ok = 1;
     long double r1 = r_of_gamma(&c, 1.0, &ok);
-    double curv = ok ? (double)(r1 - (A - (long double)deta[k])) : INFINITY;
+    /* curvature r(1) - phi(0) = B(1), the relative entropy of u_old + du */
+    double curv = ok ? (double)(r1 - naive) : INFINITY;
     double noise = (double)(64.0L * DBL_EPSILON * scale);
     if (phi0_out) phi0_out[k] = phi0;
     if (curv_out) curv_out[k] = curv;
@@ -236,13 +254,14 @@ typedef struct {
   const double* du;
   const double* deta;
   const double* M;
+  long double shift; /* phi(0) given - (A - D): 0 unless phi(0) is supplied */
 } glob_ctx;
 
 static long double r_global(const glob_ctx* c, double gamma, int* ok) {
   long double sum = 0.0L;
   *ok = 1;
   for (long k = 0; k < c->ne; ++k) {
-    elem_ctx e = {c->g, k, c->N, c->nd, c->nv, c->u, c->du, c->deta[k], c->M};
+    elem_ctx e = {c->g, k, c->N, c->nd, c->nv, c->u, c->du, c->deta[k], c->M, 0.0L};
     int okk = 1;
     long double r = r_of_gamma(&e, gamma, &okk);
     if (!okk) {
@@ -255,15 +274,24 @@ static long double r_global(const glob_ctx* c, double gamma, int* ok) {
 }
 
 static long double phi_global(double gamma, void* vctx, int* ok) {
-  long double r = r_global((const glob_ctx*)vctx, gamma, ok);
+  const glob_ctx* c = (const glob_ctx*)vctx;
+  long double r = r_global(c, gamma, ok);
   if (!*ok) return INFINITY;
-  return r / (long double)gamma;
+  return r / (long double)gamma + c->shift;
 }
 
 int orc_global_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
                                 const double* u_old, const double* du, const double* deta,
                                 double* gamma, double* phi0_out, double* curv_out,
                                 double* noise_out, int* iters_out) {
+  return orc_global_relaxation_solve_a(g, o, u_old, du, deta, NULL, gamma, phi0_out, curv_out,
+                                       noise_out, iters_out);
+}
+
+int orc_global_relaxation_solve_a(const orc_mesh* g, const orc_relax_opts* o,
+                                  const double* u_old, const double* du, const double* deta,
+                                  const double* a_in, double* gamma, double* phi0_out,
+                                  double* curv_out, double* noise_out, int* iters_out) {
   long N = orc_num_nodes(g), ne = orc_num_elems(g);
   if (N < 0 || !gamma) return ORC_EINVAL;
   int nd = 1, nv = g->dim + 2;
@@ -272,13 +300,14 @@ int orc_global_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
   double M[4096];
   orc__geom_mass(g, M);
   /* phi(0) = sum_i M_i w(u_old,i).du_i - sum_k deta_k and its round-off scale */
-  long double A = 0.0L, scale = 0.0L, D = 0.0L;
+  long double A = 0.0L, scale = 0.0L, D = 0.0L, asum = 0.0L;
   for (long k = 0; k < ne; ++k) {
     for (int i = 0; i < nd; ++i) {
       long gi = k * nd + i;
-      double ui[5], wi[5];
+      double ui[5];
+      long double wi[5];
       for (int v = 0; v < nv; ++v) ui[v] = u_old[v * N + gi];
-      orc_entropy_vars(g->dim, g->gas_gamma, ui, wi);
+      orc__entropy_vars_ld(g->dim, g->gas_gamma, ui, wi);
       for (int v = 0; v < nv; ++v) {
         long double t = (long double)M[i] * wi[v] * du[v * N + gi];
         A += t;
@@ -287,12 +316,16 @@ int orc_global_relaxation_solve(const orc_mesh* g, const orc_relax_opts* o,
     }
     D += deta[k];
     scale += fabsl((long double)deta[k]);
+    if (a_in) asum += a_in[k];
   }
-  glob_ctx c = {g, N, ne, nd, nv, u_old, du, deta, M};
+  /* phi(0) = A - D, or the sum of the supplied per-element values */
+  long double naive = A - D;
+  long double a = a_in ? asum : naive;
+  glob_ctx c = {g, N, ne, nd, nv, u_old, du, deta, M, a - naive};
   int ok = 1;
-  double phi0 = (double)(A - D);
+  double phi0 = (double)a;
   long double r1 = r_global(&c, 1.0, &ok);
-  double curv = ok ? (double)(r1 - (A - D)) : INFINITY;
+  double curv = ok ? (double)(r1 - naive) : INFINITY;
   double noise = (double)(64.0L * DBL_EPSILON * scale);
   if (phi0_out) *phi0_out = phi0;
   if (curv_out) *curv_out = curv;
@@ -327,6 +360,7 @@ long double orc_global_relax_r(const orc_mesh* g, const double* u_old, const dou
   c.du = du;
   c.deta = deta;
   c.M = M;
+  c.shift = 0.0L;
   int ok = 1;
   long double r = r_global(&c, gamma, &ok);
   if (admissible) *admissible = ok;

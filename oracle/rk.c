@@ -139,9 +139,13 @@ int orc_tableau_stages(int which) {
   return get_tableau(which, &T) ? -1 : T.s;
 }
 
+/* internal helpers (euler.c, relax.c) */
+void orc__entropy_vars_ld(int dim, double gg, const double* q, long double* w);
+int orc__geom_mass(const orc_mesh* g, double* M);
+
 static int rk_step_impl(const orc_mesh* g, int which, const double* u_old, double dt,
                         double* du, double* deta, double* ystages, double* kstages,
-                        double* estages, double* err) {
+                        double* estages, double* err, double* a_out) {
   tableau T;
   if (get_tableau(which, &T)) return ORC_EINVAL;
   if (err && T.q == 0) return ORC_EINVAL;
@@ -178,6 +182,53 @@ static int rk_step_impl(const orc_mesh* g, int which, const double* u_old, doubl
       for (int i = 0; i < T.s; ++i) acc += T.b[i] * E[i * ne + k];
       deta[k] = dt * acc;
     }
+    /* phi_k(0) = sum_i M w(u_old).du - deta_k written without the cancelling
+     * difference: dt sum_i b_i sum_nodes M (w(u_old) - w(y^i)).k_i, with
+     * the entropy variables in extended precision (an identity of the
+     * estimate's definition; the y^i are recomputed from the stored slopes) */
+    if (a_out) {
+      int nd = 1, nv = g->dim + 2;
+      for (int m = 0; m < g->dim; ++m) nd *= g->deg + 1;
+      double* M = (double*)malloc(sizeof(double) * nd);
+      long double* acc = (long double*)calloc(ne, sizeof(long double));
+      if (!M || !acc) {
+        free(M);
+        free(acc);
+        free(K);
+        free(E);
+        free(y);
+        return ORC_EINVAL;
+      }
+      orc__geom_mass(g, M);
+      for (int i = 1; i < T.s; ++i) {
+        if (T.b[i] == 0.0) continue;
+        for (long q = 0; q < len; ++q) {
+          double a = 0.0;
+          for (int j = 0; j < i; ++j) a += T.A[i][j] * K[j * len + q];
+          y[q] = u_old[q] + dt * a;
+        }
+        for (long k = 0; k < ne; ++k) {
+          long double s = 0.0L;
+          for (int n = 0; n < nd; ++n) {
+            long gi = k * nd + n;
+            double uo[5], yi[5];
+            long double w0[5], w1[5];
+            for (int v = 0; v < nv; ++v) {
+              uo[v] = u_old[v * N + gi];
+              yi[v] = y[v * N + gi];
+            }
+            orc__entropy_vars_ld(g->dim, g->gas_gamma, uo, w0);
+            orc__entropy_vars_ld(g->dim, g->gas_gamma, yi, w1);
+            for (int v = 0; v < nv; ++v)
+              s += (long double)M[n] * (w0[v] - w1[v]) * K[i * len + v * N + gi];
+          }
+          acc[k] += (long double)T.b[i] * s;
+        }
+      }
+      for (long k = 0; k < ne; ++k) a_out[k] = (double)((long double)dt * acc[k]);
+      free(M);
+      free(acc);
+    }
     /* local error estimate u_new - uhat_new = dt sum_i (b_i - bhat_i) k_i */
     if (err)
       for (long q = 0; q < len; ++q) {
@@ -197,12 +248,17 @@ static int rk_step_impl(const orc_mesh* g, int which, const double* u_old, doubl
 int orc_rk_step(const orc_mesh* g, int which, const double* u_old, double dt,
                 double* du, double* deta, double* ystages, double* kstages,
                 double* estages) {
-  return rk_step_impl(g, which, u_old, dt, du, deta, ystages, kstages, estages, NULL);
+  return rk_step_impl(g, which, u_old, dt, du, deta, ystages, kstages, estages, NULL, NULL);
+}
+
+int orc_rk_step_a(const orc_mesh* g, int which, const double* u_old, double dt, double* du,
+                  double* deta, double* a_out) {
+  return rk_step_impl(g, which, u_old, dt, du, deta, NULL, NULL, NULL, NULL, a_out);
 }
 
 int orc_rk_step_err(const orc_mesh* g, int which, const double* u_old, double dt,
                     double* du, double* deta, double* err) {
-  return rk_step_impl(g, which, u_old, dt, du, deta, NULL, NULL, NULL, err);
+  return rk_step_impl(g, which, u_old, dt, du, deta, NULL, NULL, NULL, err, NULL);
 }
 
 double orc_error_norm(const orc_mesh* g, const double* u_old, const double* du,
@@ -241,18 +297,19 @@ int orc_adaptive_step(const orc_mesh* g, int which, const orc_relax_opts* o, int
   double* er = (double*)malloc(sizeof(double) * len);
   double* deta = (double*)malloc(sizeof(double) * ne);
   double* gk = (double*)malloc(sizeof(double) * ne);
-  int rc = (du && er && deta && gk) ? ORC_OK : ORC_EINVAL;
-  if (rc == ORC_OK) rc = rk_step_impl(g, which, u, dt, du, deta, NULL, NULL, NULL, er);
+  double* a = (double*)malloc(sizeof(double) * ne);
+  int rc = (du && er && deta && gk && a) ? ORC_OK : ORC_EINVAL;
+  if (rc == ORC_OK) rc = rk_step_impl(g, which, u, dt, du, deta, NULL, NULL, NULL, er, a);
   double en = 0.0, gam = 1.0;
   int acc = 0;
   if (rc == ORC_OK) {
     en = orc_error_norm(g, u, du, er, atol, rtol);
     acc = en <= 1.0;
     if (acc && mode == 0)
-      rc = orc_local_relaxation_solve(g, o, u, du, deta, gk, &gam, NULL, NULL, NULL, NULL,
-                                      NULL);
+      rc = orc_local_relaxation_solve_a(g, o, u, du, deta, a, gk, &gam, NULL, NULL, NULL, NULL,
+                                        NULL);
     else if (acc && mode == 1)
-      rc = orc_global_relaxation_solve(g, o, u, du, deta, &gam, NULL, NULL, NULL, NULL);
+      rc = orc_global_relaxation_solve_a(g, o, u, du, deta, a, &gam, NULL, NULL, NULL, NULL);
   }
   if (rc == ORC_OK && acc) {
     for (long q = 0; q < len; ++q) u[q] = u[q] + gam * du[q];
@@ -269,6 +326,7 @@ int orc_adaptive_step(const orc_mesh* g, int which, const orc_relax_opts* o, int
   free(er);
   free(deta);
   free(gk);
+  free(a);
   return rc;
 }
 
@@ -282,17 +340,19 @@ int orc_step(const orc_mesh* g, int which, const orc_relax_opts* o, double cfl,
   double* du = (double*)malloc(sizeof(double) * len);
   double* deta = (double*)malloc(sizeof(double) * ne);
   double* gk = (double*)malloc(sizeof(double) * ne);
-  if (!du || !deta || !gk) {
+  double* a = (double*)malloc(sizeof(double) * ne);
+  if (!du || !deta || !gk || !a) {
     free(du);
     free(deta);
     free(gk);
+    free(a);
     return ORC_EINVAL;
   }
   double gam = 1.0;
-  int rc = orc_rk_step(g, which, u, dt, du, deta, NULL, NULL, NULL);
+  int rc = orc_rk_step_a(g, which, u, dt, du, deta, a);
   if (rc == ORC_OK)
-    rc = orc_local_relaxation_solve(g, o, u, du, deta, gk, &gam, NULL, NULL, NULL, NULL,
-                                    bad_elem);
+    rc = orc_local_relaxation_solve_a(g, o, u, du, deta, a, gk, &gam, NULL, NULL, NULL, NULL,
+                                      bad_elem);
   if (rc == ORC_OK) {
     for (long q = 0; q < len; ++q) u[q] = u[q] + gam * du[q];
     *t = *t + gam * dt;
@@ -303,5 +363,6 @@ int orc_step(const orc_mesh* g, int which, const orc_relax_opts* o, double cfl,
   free(du);
   free(deta);
   free(gk);
+  free(a);
   return rc;
 }
