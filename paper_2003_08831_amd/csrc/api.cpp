@@ -27,6 +27,7 @@ struct esrk_ctx {
   double* kst = nullptr;    // slope store (nslots x nv x N)
   double* err = nullptr;    // embedded pairs: error estimate (nv x N)
   double* errk = nullptr;   // embedded pairs: per-element squared weighted errors
+  double* phi0acc = nullptr;  // phi_k(0) accumulated by the stages
   double atol = 0.0, rtol = 0.0;  // error control (both 0: off)
   bool have_dt_next = false;      // a proposal from the last controlled attempt exists
   size_t N, ne;
@@ -188,6 +189,7 @@ hipError_t viscous(esrk_ctx* x, const double* y, double* diss, hipStream_t s) {
 void stage_extras(const esrk_ctx* x, int stage, bool last, esrk::RhsArgs& a) {
   a.kst = x->kst;
   a.row = x->rows[stage];
+  a.phi0 = x->phi0acc;
   if (x->order_emb > 0) {
     a.err = x->err;
     if (last && (x->atol > 0.0 || x->rtol > 0.0)) {
@@ -211,13 +213,14 @@ void stage_extras(const esrk_ctx* x, int stage, bool last, esrk::RhsArgs& a) {
 // the solve (a non-physical stage state, say) is returned as it is and stays
 // latched.
 esrk_status global_solve(esrk_ctx* x, const double* u_old, const double* du, const double* deta,
-                         double* gamma_host, int* passes_out, bool check_latched,
-                         bool check_reject, hipStream_t s) {
+                         const double* phi0_in, double* gamma_host, int* passes_out,
+                         bool check_latched, bool check_reject, hipStream_t s) {
   double o[esrk::kGlobParts];
   int passes = 0, latched = 0, rejected = 0;
   auto eval = [&](int first, const esrk::GlobTrials& t) -> bool {
     ++passes;
-    if (esrk::launch_glob_eval(x->mp, u_old, du, deta, first, t, x->glob_parts, x->glob_out,
+    if (esrk::launch_glob_eval(x->mp, u_old, du, deta, phi0_in, first, t, x->glob_parts,
+                               x->glob_out,
                                s) != hipSuccess)
       return false;
     if (hipMemcpyAsync(o, x->glob_out, sizeof(o), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -408,6 +411,7 @@ esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
             hipMalloc(&x->yb, len * sizeof(double)) == hipSuccess &&
             hipMalloc(&x->du, len * sizeof(double)) == hipSuccess &&
             hipMalloc(&x->deta, ne * sizeof(double)) == hipSuccess &&
+            hipMalloc(&x->phi0acc, ne * sizeof(double)) == hipSuccess &&
             hipMalloc(&x->gamma_k, ne * sizeof(double)) == hipSuccess &&
             hipMalloc(&x->iters, ne * sizeof(int32_t)) == hipSuccess &&
             hipMalloc(&x->speed_parts, esrk::kSpeedBlocks * sizeof(double)) == hipSuccess &&
@@ -463,6 +467,7 @@ void esrk_destroy(esrk_ctx* x) {
   (void)hipFree(x->kst);
   (void)hipFree(x->err);
   (void)hipFree(x->errk);
+  (void)hipFree(x->phi0acc);
   (void)hipFree(x->scal);
   delete x;
 }
@@ -623,12 +628,13 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
     r.dt_dev = &x->scal->dt;
     r.vfeat = x->cfg.mu > 0.0 ? x->vdiss : nullptr;
     r.check_reject = adaptive ? 1 : 0;
+    r.phi0_in = x->phi0acc;
     e = esrk::launch_relax(x->mp, r, s);
   } else {
     double g = INFINITY;  // +inf partial: the update takes gamma = 1
     if (x->relax_mode == ESRK_RELAX_GLOBAL) {
       const esrk_status st =
-          global_solve(x, u, x->du, x->deta, &g, nullptr, true, adaptive, s);
+          global_solve(x, u, x->du, x->deta, x->phi0acc, &g, nullptr, true, adaptive, s);
       if (st != ESRK_OK) return st;
     }
     e = esrk::launch_set_part(x->relax_parts, g, s);
@@ -679,7 +685,7 @@ esrk_status esrk_global_relaxation_solve(esrk_ctx* x, const double* u_old, const
   hipStream_t s = (hipStream_t)stream;
   x->last = s;
   double g = 1.0;
-  const esrk_status st = global_solve(x, u_old, du, deta, &g, passes, false, false, s);
+  const esrk_status st = global_solve(x, u_old, du, deta, nullptr, &g, passes, false, false, s);
   if (st != ESRK_OK) return st;
   if (hipMemcpyAsync(gamma, &g, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)

@@ -42,6 +42,7 @@ struct esrk_batch {
   int2* node_items = nullptr;  // 256-node chunks (wave speed, update)
   int n_node_items = 0;
   double *ya = nullptr, *yb = nullptr, *du = nullptr, *deta = nullptr, *gamma_k = nullptr;
+  double* phi0acc = nullptr;  // phi_k(0) accumulated by the stages
   int32_t* iters = nullptr;
   double* speed_parts = nullptr;
   RelaxPart* relax_parts = nullptr;
@@ -105,6 +106,7 @@ hipError_t enqueue_step(esrk_batch* b, double* u, double* t, double* gamma, int 
     a.out = last ? nullptr : bufs[i & 1];
     a.du = b->du;
     a.eta = b->deta;
+    a.phi0 = b->phi0acc;
     a.speed_parts = i == 0 ? b->speed_parts : nullptr;
     a.sc = b->sc[i];
     a.stage_mode = 1;
@@ -121,6 +123,7 @@ hipError_t enqueue_step(esrk_batch* b, double* u, double* t, double* gamma, int 
     r.u_old = u;
     r.du = b->du;
     r.deta = b->deta;
+    r.phi0_in = b->phi0acc;
     r.guess = nullptr;
     r.gamma_k = b->gamma_k;
     r.iters = b->iters;
@@ -253,6 +256,7 @@ esrk_status esrk_batch_create(const esrk_config* cfgs, int nsims, esrk_batch** o
        hipMalloc(&b->yb, b->len * sizeof(double)) == hipSuccess &&
        hipMalloc(&b->du, b->len * sizeof(double)) == hipSuccess &&
        hipMalloc(&b->deta, b->nelems * sizeof(double)) == hipSuccess &&
+       hipMalloc(&b->phi0acc, b->nelems * sizeof(double)) == hipSuccess &&
        hipMalloc(&b->gamma_k, b->nelems * sizeof(double)) == hipSuccess &&
        hipMalloc(&b->iters, b->nelems * sizeof(int32_t)) == hipSuccess &&
        hipMalloc(&b->speed_parts, std::max(1, b->n_node_items) * sizeof(double)) == hipSuccess &&
@@ -286,6 +290,7 @@ void esrk_batch_destroy(esrk_batch* b) {
   (void)hipFree(b->yb);
   (void)hipFree(b->du);
   (void)hipFree(b->deta);
+  (void)hipFree(b->phi0acc);
   (void)hipFree(b->gamma_k);
   (void)hipFree(b->iters);
   (void)hipFree(b->speed_parts);

@@ -193,4 +193,53 @@ __device__ __forceinline__ void ec_flux_from_means(int m, const Prim<T, DIM>& A,
   F[DIM + 1] = fe;
 }
 
+// ln(1 + x) without cancellation for small |x|: 2 atanh(t), t = x / (2 + x),
+// by its series (|x| < 0.1: |t| < 0.048, first dropped term below 1e-21
+// relative); log_d(1 + x) beyond, where its absolute error of a few ulp is a
+// relative error of at most a few tens of ulp.
+__device__ __forceinline__ double log1p_d(double x) {
+  if (fabs(x) < 0.1) {
+    const double t = x * rcp(2.0 + x);
+    return 2.0 * t * atanh_over<double, 8>(t * t);
+  }
+  return log_d(1.0 + x);
+}
+
+// Change of the entropy variables w = [(g - s)/(g - 1) - K/p, m/p, -rho/p]
+// (s = ln p - g ln rho, K = |m|^2/(2 rho)) from state u to state y, written
+// in the differences d = y - u so that it keeps its relative accuracy however
+// small d is:
+//   dK = (rho (2 m.dm + |dm|^2) - drho |m|^2) / (2 rho rho'),
+//   dp = (g - 1)(dE - dK),
+//   d(-rho/p) = (rho dp - drho p) / (p p'),   d(m/p) = (dm p - m dp) / (p p'),
+//   d(K/p) = (dK p - K dp) / (p p'),
+//   ds = ln(1 + dp/p) - g ln(1 + drho/rho).
+template <int DIM>
+__device__ __forceinline__ void entropy_var_change(const double* u, const double* y, double gg,
+                                                   double* dw) {
+  const double rho = u[0], dr = y[0] - u[0];
+  const double dE = y[DIM + 1] - u[DIM + 1];
+  double m2 = 0.0, mdm = 0.0, dm2 = 0.0, dm[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    dm[d] = y[1 + d] - u[1 + d];
+    m2 += u[1 + d] * u[1 + d];
+    mdm += u[1 + d] * dm[d];
+    dm2 += dm[d] * dm[d];
+  }
+  const double ir = rcp(rho), ir1 = rcp(y[0]);
+  const double K = 0.5 * m2 * ir;
+  const double gm1 = gg - 1.0;
+  const double p = gm1 * (u[DIM + 1] - K);
+  const double dK = 0.5 * (rho * (2.0 * mdm + dm2) - dr * m2) * ir * ir1;
+  const double dp = gm1 * (dE - dK);
+  const double ip = rcp(p);
+  const double ipp = ip * rcp(p + dp);
+  dw[DIM + 1] = (rho * dp - dr * p) * ipp;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) dw[1 + d] = (dm[d] * p - u[1 + d] * dp) * ipp;
+  const double ds = log1p_d(dp * ip) - gg * log1p_d(dr * ir);
+  dw[0] = -ds * rcp(gm1) - (dK * p - K * dp) * ipp;
+}
+
 }  // namespace esrk

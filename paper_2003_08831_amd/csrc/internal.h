@@ -131,6 +131,9 @@ struct RhsArgs {
   // (err / (atol + rtol max(|u_old|, |u_old + du|)))^2 (nullable)
   double* errk;
   double atol, rtol;
+  // stage mode (nullable): phi_k(0) accumulated without cancellation,
+  // phi (+)= b dt sum_nodes M (w(u_old) - w(y)).k  (stage 0 writes 0)
+  double* phi0;
 };
 
 // Host tables (Lobatto nodes/weights/derivative matrix), built in extended
@@ -172,6 +175,8 @@ struct RelaxArgs {
   int fp32_increments;
   // error-controlled steps: nothing to solve when scal->rejected is set
   int check_reject;
+  // nullable: phi_k(0) per element from the stages (else A_k - deta_k)
+  const double* phi0_in;
 };
 int relax_blocks(const MeshParams& mp);
 
@@ -183,9 +188,11 @@ struct GlobTrials {
   double g[kGlobTrials];
 };
 int glob_blocks(const MeshParams& mp);
+// phi0_in (nullable): per-element phi_k(0), summed in place of A - sum deta
 hipError_t launch_glob_eval(const MeshParams& mp, const double* u_old, const double* du,
-                            const double* deta, int first, const GlobTrials& trials,
-                            double* parts, double* out, hipStream_t s);
+                            const double* deta, const double* phi0_in, int first,
+                            const GlobTrials& trials, double* parts, double* out,
+                            hipStream_t s);
 hipError_t launch_set_part(RelaxPart* parts, double g, hipStream_t s);
 hipError_t launch_relax(const MeshParams& mp, const RelaxArgs& a, hipStream_t s);
 // gamma = min over partials (1 if all inactive) -> *gamma and scal->gamma

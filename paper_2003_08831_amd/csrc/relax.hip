@@ -257,7 +257,7 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
   scale = seg_sum<G>(scale);
   if (want_feats) smax = seg_max<G>(smax);
   const double deta = valid ? a.deta[k] : 0.0;
-  const double phi0 = A - deta;
+  const double phi0 = a.phi0_in ? (valid ? a.phi0_in[k] : 0.0) : A - deta;
   // round-off level of the element's entropy increments: FP64 increments, or
   // increments built from FP32 flux differences (then the estimate and the
   // update of an element that barely changes are FP32 noise and its root is
@@ -503,6 +503,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     a.u_old = a0.u_old + P.base;
     a.du = a0.du + P.base;
     a.deta = a0.deta + P.elem_base;
+    a.phi0_in = a0.phi0_in ? a0.phi0_in + P.elem_base : nullptr;
     a.guess = a0.guess ? a0.guess + P.elem_base : nullptr;
     a.gamma_k = a0.gamma_k + P.elem_base;
     a.iters = a0.iters ? a0.iters + P.elem_base : nullptr;
@@ -767,8 +768,8 @@ hipError_t launch_adapt(const double* errk, int ne, double count, int q, int dec
 template <int DIM, int N>
 __global__ void __launch_bounds__(256) glob_eval_kernel(const MeshParams mp, const double* u_old,
                                                         const double* du, const double* deta,
-                                                        int first, GlobTrials trials,
-                                                        double* parts) {
+                                                        const double* phi0_in, int first,
+                                                        GlobTrials trials, double* parts) {
   constexpr int ND = (DIM == 1) ? N : (DIM == 2) ? N * N : N * N * N;
   constexpr int NV = DIM + 2;
   const MeshDims md = dims_of(mp);
@@ -826,11 +827,16 @@ __global__ void __launch_bounds__(256) glob_eval_kernel(const MeshParams mp, con
       const double te = -2.0 * beta * dE;
       t += te;
       sc += fabs(te);
-      acc[0] = M * t;
       acc[1] = M * sc;
+      if (phi0_in) {
+        // phi(0) = sum_k phi_k(0) from the stages; the scale stays
+        acc[0] = (i == 0) ? phi0_in[gi / ND] : 0.0;
+      } else {
+        acc[0] = M * t;
+      }
       if (i == 0) {
         const double de = deta[gi / ND];
-        acc[2] = de;
+        acc[2] = phi0_in ? 0.0 : de;
         acc[3] = fabs(de);
       }
     }
@@ -919,12 +925,13 @@ __global__ void set_part_kernel(RelaxPart* parts, double g) {
 int glob_blocks(const MeshParams& mp) { return (mp.ne * mp.nd + 255) / 256; }
 
 hipError_t launch_glob_eval(const MeshParams& mp, const double* u_old, const double* du,
-                            const double* deta, int first, const GlobTrials& trials,
-                            double* parts, double* out, hipStream_t s) {
+                            const double* deta, const double* phi0_in, int first,
+                            const GlobTrials& trials, double* parts, double* out,
+                            hipStream_t s) {
   const int blocks = glob_blocks(mp);
 #define ESRK_GE(D, NN)                                                                  \
   hipLaunchKernelGGL((glob_eval_kernel<D, NN>), dim3(blocks), dim3(256), 0, s, mp, u_old, \
-                     du, deta, first, trials, parts)
+                     du, deta, phi0_in, first, trials, parts)
 #define ESRK_GD(D)                     \
   switch (mp.n) {                      \
     case 2: ESRK_GE(D, 2); break;      \

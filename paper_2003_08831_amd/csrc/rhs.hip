@@ -354,14 +354,15 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
     if (a.first && k0 == 0 && tid == 0 && a.dt_store) *a.dt_store = dt;
   }
   const bool want_y = a.stage_mode && a.out && a.sc.beta != 0.0;
-  const bool want_uold = a.stage_mode && (a.out || a.errk);
+  const bool want_uold = a.stage_mode && (a.out || a.errk || a.phi0);
+  const bool want_psi = a.stage_mode && a.phi0 && !a.first;
   const bool want_du = a.stage_mode && !a.first;
   // weighted squared error per node of this thread (last stage of an
   // error-controlled step), reduced per element after the entropy rates
   constexpr int ITER = (EN + TH - 1) / TH;
-  double esq[ITER];
+  double esq[ITER], psi[ITER];
 #pragma unroll
-  for (int it = 0; it < ITER; ++it) esq[it] = 0.0;
+  for (int it = 0; it < ITER; ++it) esq[it] = psi[it] = 0.0;
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
     const int idx = tid + it * TH;
@@ -456,6 +457,15 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
         dn[v] = dp[v] + bdt * kv[v];
         a.du[v * Ntot + gi] = dn[v];
       }
+      if (want_psi) {
+        // this node's part of phi_k(0): M (w(u_old) - w(y)).k
+        double dw[NV];
+        entropy_var_change<DIM>(uo, yv, ggd, dw);
+        double s = 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s += dw[v] * kv[v];
+        psi[it] = -M * s;
+      }
       if (a.err) {
         const double edt = a.row.ecoef * dt;
 #pragma unroll
@@ -488,6 +498,24 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       }
     }
   }
+  if (a.stage_mode && a.phi0) {
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = tid + it * TH;
+      if (idx < EN) sred[idx] = psi[it];
+    }
+    __syncthreads();
+    if (tid < E) {
+      const int k = k0 + tid;
+      if (k < md.ne) {
+        double s = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < ND; ++i) s += sred[tid * ND + i];
+        a.phi0[k] = (a.first ? 0.0 : a.phi0[k]) + a.sc.b * dt * s;
+      }
+    }
+  }
   if (a.errk) {
     __syncthreads();
 #pragma unroll
@@ -500,6 +528,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       const int k = k0 + tid;
       if (k < md.ne) {
         double s = 0.0;
+#pragma unroll 8
         for (int i = 0; i < ND; ++i) s += sred[tid * ND + i];
         a.errk[k] = s;
       }
@@ -565,6 +594,7 @@ __global__ void __launch_bounds__((RhsShape<DIM, N, T, E>::THREADS))
     a.out = a0.out ? a0.out + P.base : nullptr;
     a.du = a0.du ? a0.du + P.base : nullptr;
     a.eta = a0.eta ? a0.eta + P.elem_base : nullptr;
+    a.phi0 = a0.phi0 ? a0.phi0 + P.elem_base : nullptr;
     a.speed_parts = a0.speed_parts ? a0.speed_parts + P.speed_p0 : nullptr;
     a.n_speed_parts = P.speed_p1 - P.speed_p0;
     a.dt_dev = dt_sims_in ? dt_sims_in + w.x : nullptr;

@@ -175,3 +175,46 @@ def test_error_controlled_attempts_parity(tab, otab, mode):
     print(f"[adaptive {PAIR_IDS[tab - 2]} mode {mode}] rejections {n_rej}")
     assert n_rej >= 1
     assert ctx.sync_status()[0] == 0
+
+
+@pytest.mark.parametrize("tab,otab", [(esrk.RK44, O.RK44), (esrk.BSRK85, O.BSRK85)],
+                         ids=["rk44", "bsrk85"])
+@pytest.mark.parametrize("name,ms,kind", [CASES[2], CASES[7], CASES[9]],
+                         ids=["d2p3_vortex", "d3p3_tgv", "d3p4"])
+def test_step_roots_from_stagewise_phi0(tab, otab, name, ms, kind):
+    """The step solves with phi_k(0) accumulated by the stages: every
+    element's root against the oracle's roots from its own stage-wise phi_k(0),
+    to a bound a thousand times tighter than the difference form allows
+    (the oracle's extended-precision level, 2^-11 of the FP64 one, plus the
+    root tolerance)."""
+    u = make_state(ms, kind, seed=5)
+    m = orc_mesh(O, ms)
+    ctx = ctx_for(ms, tableau=tab, cfl=0.5)
+    dt = O.cfl_dt(m, u, 0.5)
+    du, deta, a = O.rk_step_a(m, otab, u, dt)
+    ref = O.local_relaxation_solve(m, u, du, deta, a=a)
+    assert ref["rc"] == 0
+    gk, stats = zeros(ctx.ne), zeros(8)
+    ctx.step(dev(u), dev(np.array([0.0])), dt, gk, stats)
+    g = host(gk)
+    g_ref = ref["gamma_k"]
+    fin = np.isfinite(g_ref)
+    borderline = (ref["curv"] > 0.5 * ref["noise"]) & (ref["curv"] < 2.0 * ref["noise"])
+    assert np.array_equal(fin[~borderline], np.isfinite(g)[~borderline])
+    both = fin & np.isfinite(g) & ~borderline
+    # the two sides evaluate the right-hand side with different rounding: the
+    # slopes differ by ~1e-14 of the term scale S, which in a quiet element is
+    # a relative change rho_k of its increments, and gamma_k = -phi(0)/B'' moves
+    # by ~4 rho_k gamma_k (phi(0) and B both quadratic in the increments)
+    S = term_scale(O, ms, u)
+    d3 = np.abs(du.reshape(ms.nv, ms.ne, ms.nd)).max(axis=2)  # [v, k]
+    rho_k = (1e-14 * dt * S[:, None] / np.maximum(d3, 1e-300)).min(axis=0)
+    tol = (2e-12 * np.maximum(1.0, g_ref[both]) + 1e-3 * ref["noise"][both] / ref["curv"][both]
+           + 8.0 * rho_k[both] * g_ref[both])
+    err = np.abs(g[both] - g_ref[both])
+    w = np.argmax(err / tol)
+    print(f"[stage-wise phi0 {name}] active {both.sum()} max |dgamma| {err.max():.2e} "
+          f"bound of the difference form {(ref['noise'][both] / ref['curv'][both]).max():.2e}; "
+          f"worst element: err {err[w]:.2e} tol {tol[w]:.2e} rho {rho_k[both][w]:.2e}")
+    assert np.all(err <= tol), (err.max(), tol[np.argmax(err - tol)])
+    assert ctx.sync_status()[0] == 0
