@@ -147,6 +147,25 @@ esrk_status esrk_local_relaxation_solve(esrk_ctx* ctx, const double* u_old,
                                         const float* gamma_guess, double* gamma_k,
                                         double* gamma, int32_t* iters, void* stream);
 
+/* phi_k(0) = sum_i M w(u_old).du - deta_k of each element, accumulated by the
+ * last run of stages (esrk_rk_stage or esrk_step) without the cancelling
+ * difference: dt sum_i b_i sum_nodes M (w(u_old) - w(y^i)).k_i, with the
+ * entropy-variable changes w(y^i) - w(u_old) written in the state
+ * differences (an identity of the estimate's definition in Sec. 2; in
+ * elements with round-off-level dynamics the difference form loses its
+ * digits and such an element can set gamma = min_k gamma_k).  phi0 device
+ * [num_elems].  Enqueue only. */
+esrk_status esrk_stage_phi0(esrk_ctx* ctx, double* phi0, void* stream);
+
+/* esrk_local_relaxation_solve with phi_k(0) supplied (device [num_elems],
+ * e.g. from esrk_stage_phi0 after the stages that produced du and deta):
+ * phi_k(g) = phi0_k + B_k(g)/g.  The activity test is unchanged.  esrk_step
+ * solves this way. */
+esrk_status esrk_local_relaxation_solve_phi0(esrk_ctx* ctx, const double* u_old,
+                                             const double* du, const double* deta,
+                                             const double* phi0, double* gamma_k,
+                                             double* gamma, int32_t* iters, void* stream);
+
 /* One whole locally relaxed step, in place on u (Sec. 2: RK step, estimate,
  * gamma = min_k gamma_k, u <- u + gamma du, t <- t + gamma dt).  t is a device
  * scalar.  dt > 0 is used as given; dt <= 0 takes dt from the CFL rule on the

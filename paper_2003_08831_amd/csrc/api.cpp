@@ -569,6 +569,29 @@ esrk_status esrk_local_relaxation_solve(esrk_ctx* x, const double* u_old, const 
   return hip_status(e);
 }
 
+esrk_status esrk_local_relaxation_solve_phi0(esrk_ctx* x, const double* u_old,
+                                             const double* du, const double* deta,
+                                             const double* phi0, double* gamma_k,
+                                             double* gamma, int32_t* iters, void* stream) {
+  if (!x || !u_old || !du || !deta || !phi0 || !gamma_k || !gamma) return ESRK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  x->last = s;
+  esrk::RelaxArgs r = relax_args(x, u_old, du, deta, nullptr, gamma_k, iters);
+  r.phi0_in = phi0;
+  hipError_t e = esrk::launch_relax(x->mp, r, s);
+  if (e == hipSuccess)
+    e = esrk::launch_relax_finish(x->relax_parts, x->n_relax_parts, x->scal, gamma, s);
+  return hip_status(e);
+}
+
+esrk_status esrk_stage_phi0(esrk_ctx* x, double* phi0, void* stream) {
+  if (!x || !phi0) return ESRK_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  x->last = s;
+  return hip_status(
+      hipMemcpyAsync(phi0, x->phi0acc, x->ne * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
 esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamma_k_out,
                       double* stats_out, void* stream) {
   if (!x || !u || !t) return ESRK_EINVAL;
@@ -610,6 +633,7 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
       a.err = nullptr;
       a.errk = nullptr;
     }
+    if (x->relax_mode == ESRK_RELAX_NONE) a.phi0 = nullptr;  // nothing to solve
     e = esrk::launch_rhs(x->mp, x->cfg.precision, a, s);
     yin = bufs[i & 1];
   }

@@ -357,12 +357,16 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
   const bool want_uold = a.stage_mode && (a.out || a.errk || a.phi0);
   const bool want_psi = a.stage_mode && a.phi0 && !a.first;
   const bool want_du = a.stage_mode && !a.first;
-  // weighted squared error per node of this thread (last stage of an
-  // error-controlled step), reduced per element after the entropy rates
+  // Per node of this thread: the entropy-rate term, the phi_k(0) term and the
+  // weighted squared error (last stage of an error-controlled step), each
+  // summed per element after the loop.  When an element's nodes are a
+  // power-of-two segment of a wave the sums are butterfly shuffles within the
+  // segment; otherwise they go through LDS.
   constexpr int ITER = (EN + TH - 1) / TH;
-  double esq[ITER], psi[ITER];
+  constexpr bool kWaveRed = (ND & (ND - 1)) == 0 && ND <= 64 && TH % 64 == 0;
+  double wdv[ITER], esq[ITER], psi[ITER];
 #pragma unroll
-  for (int it = 0; it < ITER; ++it) esq[it] = psi[it] = 0.0;
+  for (int it = 0; it < ITER; ++it) wdv[it] = esq[it] = psi[it] = 0.0;
 #pragma unroll
   for (int it = 0; it < ITER; ++it) {
     const int idx = tid + it * TH;
@@ -370,7 +374,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
     const int e = idx / ND;
     const int k = k0 + e;
     if (k >= md.ne) {
-      sred[idx] = 0.0;
+      if (!kWaveRed) sred[idx] = 0.0;
       continue;
     }
     const int i = idx - e * ND;
@@ -427,7 +431,8 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
         M *= md.half_h[d] * wq;
       }
     }
-    sred[idx] = M * wdot;
+    wdv[it] = M * wdot;
+    if (!kWaveRed) sred[idx] = wdv[it];
 
     if (a.stage_mode) {
       const double cdt = a.sc.c * dt, bdt = a.sc.b * dt;
@@ -460,7 +465,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       if (want_psi) {
         // this node's part of phi_k(0): M (w(u_old) - w(y)).k
         double dw[NV];
-        entropy_var_change<DIM>(uo, yv, ggd, dw);
+        entropy_var_change<DIM>(uo, yv, ggd, inv_gm1d, dw);
         double s = 0.0;
 #pragma unroll
         for (int v = 0; v < NV; ++v) s += dw[v] * kv[v];
@@ -483,6 +488,31 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
 #pragma unroll
       for (int v = 0; v < NV; ++v) a.out[v * Ntot + gi] = kv[v];
     }
+  }
+  if constexpr (kWaveRed) {
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      double s = wdv[it], sp = psi[it], se = esq[it];
+#pragma unroll
+      for (int off = ND / 2; off >= 1; off /= 2) {
+        s += __shfl_xor(s, off, 64);
+        if (a.stage_mode && a.phi0) sp += __shfl_xor(sp, off, 64);
+        if (a.errk) se += __shfl_xor(se, off, 64);
+      }
+      const int idx = tid + it * TH;
+      const int k = k0 + idx / ND;
+      if (idx < EN && idx % ND == 0 && k < md.ne) {
+        if (a.eta) {
+          if (a.stage_mode)
+            a.eta[k] = (a.first ? 0.0 : a.eta[k]) + a.sc.b * dt * s;
+          else
+            a.eta[k] = s;
+        }
+        if (a.stage_mode && a.phi0) a.phi0[k] = (a.first ? 0.0 : a.phi0[k]) + a.sc.b * dt * sp;
+        if (a.errk) a.errk[k] = se;
+      }
+    }
+    return;
   }
   __syncthreads();
   if (tid < E) {

@@ -83,6 +83,10 @@ def load():
     L.esrk_global_relaxation_solve.restype = st
     L.esrk_set_relaxation_mode.argtypes = [vp, C.c_int]
     L.esrk_set_relaxation_mode.restype = st
+    L.esrk_stage_phi0.argtypes = [vp, vp, vp]
+    L.esrk_stage_phi0.restype = st
+    L.esrk_local_relaxation_solve_phi0.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.esrk_local_relaxation_solve_phi0.restype = st
     L.esrk_set_adaptive.argtypes = [vp, dp, dp]
     L.esrk_set_adaptive.restype = st
     L.esrk_error_estimate.argtypes = [vp, vp, vp, vp]
@@ -229,6 +233,15 @@ class Context:
 
     def set_relaxation_mode(self, mode):
         _check(load().esrk_set_relaxation_mode(self._h, int(mode)), "esrk_set_relaxation_mode")
+
+    def stage_phi0(self, phi0, stream=None):
+        _check(load().esrk_stage_phi0(self._h, _ptr(phi0), _stream(stream)), "esrk_stage_phi0")
+
+    def local_relaxation_solve_phi0(self, u_old, du, deta, phi0, gamma_k, gamma, iters=None,
+                                    stream=None):
+        _check(load().esrk_local_relaxation_solve_phi0(
+            self._h, _ptr(u_old), _ptr(du), _ptr(deta), _ptr(phi0), _ptr(gamma_k), _ptr(gamma),
+            _ptr(iters), _stream(stream)), "esrk_local_relaxation_solve_phi0")
 
     def set_adaptive(self, atol, rtol):
         _check(load().esrk_set_adaptive(self._h, float(atol), float(rtol)), "esrk_set_adaptive")

@@ -100,3 +100,6 @@ def test_error_control_entry_point_validation():
     L = esrk.load()
     assert L.esrk_set_adaptive(None, 1e-4, 1e-4) == 1
     assert L.esrk_error_estimate(None, None, None, None) == 1
+    assert L.esrk_stage_phi0(None, None, None) == 1
+    assert L.esrk_local_relaxation_solve_phi0(None, None, None, None, None, None, None, None,
+                                              None) == 1

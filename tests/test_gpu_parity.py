@@ -260,8 +260,9 @@ def test_gpu_trajectory_entropy_inequality_and_conservation(name, ms, kind):
             yout = bufs[i % 2] if i < s - 1 else None
             ctx.rk_stage(i, dt, ud, yin, yout, du, deta)
             yin = yout
-        gk, gam = zeros(ctx.ne), zeros(1)
-        ctx.local_relaxation_solve(ud, du, deta, gk, gam)
+        gk, gam, phi0 = zeros(ctx.ne), zeros(1), zeros(ctx.ne)
+        ctx.stage_phi0(phi0)
+        ctx.local_relaxation_solve_phi0(ud, du, deta, phi0, gk, gam)
         g = host(gam)[0]
         u_new = u_old + g * host(du)
         eta_new = O.elem_entropy(m, u_new)
