@@ -28,6 +28,9 @@ struct esrk_ctx {
   double* err = nullptr;    // embedded pairs: error estimate (nv x N)
   double* errk = nullptr;   // embedded pairs: per-element squared weighted errors
   double* phi0acc = nullptr;  // phi_k(0) accumulated by the stages
+  // per-stage extras of the embedded pairs in device memory:
+  // [0][stage] rows and slope store only, [1][stage] with the error estimate
+  esrk::StageExtra* ex_dev = nullptr;
   double atol = 0.0, rtol = 0.0;  // error control (both 0: off)
   bool have_dt_next = false;      // a proposal from the last controlled attempt exists
   size_t N, ne;
@@ -185,19 +188,36 @@ hipError_t viscous(esrk_ctx* x, const double* y, double* diss, hipStream_t s) {
   return esrk::launch_ns(x->mp, x->cfg.precision, n, s);
 }
 
-// The general-tableau and error-estimate part of a stage's arguments.
-void stage_extras(const esrk_ctx* x, int stage, bool last, esrk::RhsArgs& a) {
-  a.kst = x->kst;
-  a.row = x->rows[stage];
-  a.phi0 = x->phi0acc;
-  if (x->order_emb > 0) {
-    a.err = x->err;
-    if (last && (x->atol > 0.0 || x->rtol > 0.0)) {
-      a.errk = x->errk;
-      a.atol = x->atol;
-      a.rtol = x->rtol;
+// Uploads the per-stage extras (rows, slope store; error estimate in the
+// second set, with the per-element error sums on the last stage when
+// tolerances are set).  Synchronous.
+hipError_t upload_extras(esrk_ctx* x) {
+  if (x->order_emb == 0) return hipSuccess;
+  esrk::StageExtra h[2][esrk::kMaxStages];
+  std::memset(h, 0, sizeof(h));
+  const bool tol = x->atol > 0.0 || x->rtol > 0.0;
+  for (int v = 0; v < 2; ++v)
+    for (int i = 0; i < x->stages; ++i) {
+      esrk::StageExtra& E = h[v][i];
+      E.row = x->rows[i];
+      E.kst = x->kst;
+      if (v == 1) {
+        E.err = x->err;
+        if (i == x->stages - 1 && tol) {
+          E.errk = x->errk;
+          E.atol = x->atol;
+          E.rtol = x->rtol;
+        }
+      }
     }
-  }
+  return hipMemcpy(x->ex_dev, h, sizeof(h), hipMemcpyHostToDevice);
+}
+
+// The general-tableau and error-estimate part of a stage's arguments
+// (with_err: accumulate the embedded pair's estimate).
+void stage_extras(const esrk_ctx* x, int stage, bool with_err, esrk::RhsArgs& a) {
+  a.phi0 = x->phi0acc;
+  a.ex = x->ex_dev ? x->ex_dev + (with_err ? esrk::kMaxStages : 0) + stage : nullptr;
 }
 
 // Global relaxation (one gamma with eta(u_old + gamma du) = eta(u_old) +
@@ -432,7 +452,8 @@ esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
     ok = ok && hipMalloc(&x->kst, (size_t)x->nslots * len * sizeof(double)) == hipSuccess;
   if (x->order_emb > 0)
     ok = ok && hipMalloc(&x->err, len * sizeof(double)) == hipSuccess &&
-         hipMalloc(&x->errk, ne * sizeof(double)) == hipSuccess;
+         hipMalloc(&x->errk, ne * sizeof(double)) == hipSuccess &&
+         hipMalloc(&x->ex_dev, 2 * esrk::kMaxStages * sizeof(esrk::StageExtra)) == hipSuccess;
   if (!ok) {
     esrk_destroy(x);
     return ESRK_ENOMEM;
@@ -441,7 +462,8 @@ esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
   std::memset(&init, 0, sizeof(init));
   init.bad_elem = INT64_MAX;
   init.gamma = 1.0;
-  if (hipMemcpy(x->scal, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemcpy(x->scal, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess ||
+      upload_extras(x) != hipSuccess) {
     esrk_destroy(x);
     return ESRK_EHIP;
   }
@@ -468,6 +490,7 @@ void esrk_destroy(esrk_ctx* x) {
   (void)hipFree(x->err);
   (void)hipFree(x->errk);
   (void)hipFree(x->phi0acc);
+  (void)hipFree(x->ex_dev);
   (void)hipFree(x->scal);
   delete x;
 }
@@ -531,7 +554,7 @@ esrk_status esrk_rk_stage(esrk_ctx* x, int stage, double dt, const double* u_old
   a.sc = x->sc[stage];
   a.stage_mode = 1;
   a.first = stage == 0;
-  stage_extras(x, stage, last, a);
+  stage_extras(x, stage, true, a);
   return hip_status(esrk::launch_rhs(x->mp, x->cfg.precision, a, s));
 }
 
@@ -628,11 +651,7 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
     a.sc = x->sc[i];
     a.stage_mode = 1;
     a.first = i == 0;
-    stage_extras(x, i, last, a);
-    if (!adaptive) {
-      a.err = nullptr;
-      a.errk = nullptr;
-    }
+    stage_extras(x, i, adaptive, a);
     if (x->relax_mode == ESRK_RELAX_NONE) a.phi0 = nullptr;  // nothing to solve
     e = esrk::launch_rhs(x->mp, x->cfg.precision, a, s);
     yin = bufs[i & 1];
@@ -677,7 +696,7 @@ esrk_status esrk_set_adaptive(esrk_ctx* x, double atol, double rtol) {
   x->atol = atol;
   x->rtol = rtol;
   x->have_dt_next = false;
-  return ESRK_OK;
+  return hip_status(upload_extras(x));
 }
 
 esrk_status esrk_error_estimate(esrk_ctx* x, double* err, double* norm, void* stream) {

@@ -105,6 +105,18 @@ struct StageRow {
   double ecoef;             // b_i - bhat_i (embedded pairs)
 };
 
+// The part of a stage's arguments that only general tableaux and embedded
+// pairs use.
+struct StageExtra {
+  StageRow row;
+  double* kst;   // slope store, slot j at kst + j nv N
+  double* err;   // nullable: err (+)= ecoef dt k, stage 0 overwrites
+  // nullable (last stage): per element, sum over nodes and variables of
+  // (err / (atol + rtol max(|u_old|, |u_old + du|)))^2
+  double* errk;
+  double atol, rtol;
+};
+
 struct RhsArgs {
   const double* y;      // state the right-hand side is evaluated at
   const double* u_old;  // stage mode: step start state
@@ -122,15 +134,10 @@ struct RhsArgs {
   int stage_mode;       // 0: plain right-hand side, 1: RK stage
   int first;            // stage 0 overwrites du/deta
   DevScalars* scal;
-  // general explicit tableaux (stage mode): slope store, slot j at kst + j nv N
-  double* kst;          // nullable when the tableau needs no stored slopes
-  StageRow row;
-  // embedded pairs (stage mode): err (+)= ecoef dt k, stage 0 overwrites
-  double* err;          // nullable
-  // last stage: per element, sum over nodes and variables of
-  // (err / (atol + rtol max(|u_old|, |u_old + du|)))^2 (nullable)
-  double* errk;
-  double atol, rtol;
+  // stage mode (nullable): general tableau rows and error estimate, in device
+  // memory (read in the epilogue only, so they hold no scalar registers
+  // through the flux phases)
+  const StageExtra* ex;
   // stage mode (nullable): phi_k(0) accumulated without cancellation,
   // phi (+)= b dt sum_nodes M (w(u_old) - w(y)).k  (stage 0 writes 0)
   double* phi0;

@@ -354,7 +354,10 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
     if (a.first && k0 == 0 && tid == 0 && a.dt_store) *a.dt_store = dt;
   }
   const bool want_y = a.stage_mode && a.out && a.sc.beta != 0.0;
-  const bool want_uold = a.stage_mode && (a.out || a.errk || a.phi0);
+  const StageExtra* ex = a.stage_mode ? a.ex : nullptr;
+  double* const errk = ex ? ex->errk : nullptr;
+  double* const errv = ex ? ex->err : nullptr;
+  const bool want_uold = a.stage_mode && (a.out || errk || a.phi0);
   const bool want_psi = a.stage_mode && a.phi0 && !a.first;
   const bool want_du = a.stage_mode && !a.first;
   // Per node of this thread: the entropy-rate term, the phi_k(0) term and the
@@ -445,14 +448,14 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
           // general tableaux: the earlier stored slopes of this row
 #pragma unroll
           for (int j = 0; j < kMaxPrev; ++j)
-            if (j < a.row.nprev && a.kst)
-              y += (a.row.prev_a[j] * dt) *
-                   a.kst[a.row.prev_slot[j] * slot_len + (size_t)v * Ntot + gi];
+            if (ex && j < ex->row.nprev)
+              y += (ex->row.prev_a[j] * dt) *
+                   ex->kst[ex->row.prev_slot[j] * slot_len + (size_t)v * Ntot + gi];
           a.out[v * Ntot + gi] = y;
         }
       }
-      if (a.row.kstore > 0 && a.kst) {
-        double* ks = a.kst + (size_t)(a.row.kstore - 1) * slot_len;
+      if (ex && ex->row.kstore > 0) {
+        double* ks = ex->kst + (size_t)(ex->row.kstore - 1) * slot_len;
 #pragma unroll
         for (int v = 0; v < NV; ++v) ks[(size_t)v * Ntot + gi] = kv[v];
       }
@@ -471,14 +474,15 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
         for (int v = 0; v < NV; ++v) s += dw[v] * kv[v];
         psi[it] = -M * s;
       }
-      if (a.err) {
-        const double edt = a.row.ecoef * dt;
+      if (errv) {
+        const double edt = ex->row.ecoef * dt;
+        const double atol = ex->atol, rtol = ex->rtol;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          const double ev = (a.first ? 0.0 : a.err[v * Ntot + gi]) + edt * kv[v];
-          a.err[v * Ntot + gi] = ev;
-          if (a.errk) {
-            const double sc = a.atol + a.rtol * fmax(fabs(uo[v]), fabs(uo[v] + dn[v]));
+          const double ev = (a.first ? 0.0 : errv[v * Ntot + gi]) + edt * kv[v];
+          errv[v * Ntot + gi] = ev;
+          if (errk) {
+            const double sc = atol + rtol * fmax(fabs(uo[v]), fabs(uo[v] + dn[v]));
             const double q = ev / sc;
             esq[it] += q * q;
           }
@@ -497,7 +501,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       for (int off = ND / 2; off >= 1; off /= 2) {
         s += __shfl_xor(s, off, 64);
         if (a.stage_mode && a.phi0) sp += __shfl_xor(sp, off, 64);
-        if (a.errk) se += __shfl_xor(se, off, 64);
+        if (errk) se += __shfl_xor(se, off, 64);
       }
       const int idx = tid + it * TH;
       const int k = k0 + idx / ND;
@@ -509,7 +513,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
             a.eta[k] = s;
         }
         if (a.stage_mode && a.phi0) a.phi0[k] = (a.first ? 0.0 : a.phi0[k]) + a.sc.b * dt * sp;
-        if (a.errk) a.errk[k] = se;
+        if (errk) errk[k] = se;
       }
     }
     return;
@@ -546,7 +550,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       }
     }
   }
-  if (a.errk) {
+  if (errk) {
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
@@ -560,7 +564,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
         double s = 0.0;
 #pragma unroll 8
         for (int i = 0; i < ND; ++i) s += sred[tid * ND + i];
-        a.errk[k] = s;
+        errk[k] = s;
       }
     }
   }
