@@ -228,6 +228,40 @@ def relax_modes_variant(esrk, I, torch, steps=10, warmup=2):
     return out
 
 
+def root_methods_variant(esrk, I, torch, steps=10, warmup=2):
+    """The headline workload (FP64, local relaxation) with each root-solve
+    rule: wall time per step and phi evaluations per active element."""
+    ms = I.tgv_mesh(NEL, DEG)
+    cfg = esrk.make_config(ms.dim, ms.deg, ms.nel, ms.lo, ms.hi, gas_gamma=ms.gas_gamma,
+                           precision=esrk.FP64, tableau=esrk.RK44, cfl=0.5)
+    out = {}
+    for name, method in (("illinois", esrk.ROOT_ILLINOIS), ("brent", esrk.ROOT_BRENT),
+                         ("bisection", esrk.ROOT_BISECTION)):
+        ctx = esrk.Context(cfg)
+        ctx.set_root_method(method)
+        u = torch.as_tensor(I.tgv_state(ms, MACH)).to("cuda")
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            ctx.step(u, t, 0.0, None, stats)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        evals = 0.0
+        active = 0.0
+        for _ in range(steps):
+            ctx.step(u, t, 0.0, None, stats)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - w0
+        st = stats.cpu().numpy()
+        active = ctx.ne - st[3]
+        evals = st[5] / active if active > 0 else 0.0
+        out[name] = {"ms_per_step": round(el * 1e3 / steps, 4),
+                     "phi_evals_per_active_elem": round(float(evals), 3),
+                     "max_evals": int(st[4])}
+        del ctx, u
+    return out
+
+
 def time_stage_kernel(esrk, torch, ctx, u, reps):
     """Average duration of one fused stage-kernel launch (middle RK stage),
     HIP events on the launch stream (the default stream)."""
@@ -344,6 +378,7 @@ def main():
             "kh_batch_256_fp32_graph": batch_variant(esrk, I, torch, 20),
             "learned_guess_ns_tgv": mlp_variant(esrk, I, torch, learn),
             "relaxation_modes_tgv16_p3_fp64": relax_modes_variant(esrk, I, torch),
+            "root_methods_tgv16_p3_fp64": root_methods_variant(esrk, I, torch),
         }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(I, a.cpu_steps)

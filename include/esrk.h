@@ -60,6 +60,10 @@ enum { ESRK_FP64 = 0, ESRK_FP32_FLUX = 1 };
  * their last stage at the propagated solution with weight zero: without error
  * control esrk_step skips that stage. */
 enum { ESRK_SSPRK33 = 0, ESRK_RK44 = 1, ESRK_BSRK43 = 2, ESRK_BSRK85 = 3 };
+/* Trial-point rule of the relaxation root solves (esrk_set_root_method): all
+ * keep the bracket [lo, hi] with phi(lo) <= 0 < phi(hi) and stop at the same
+ * width, so they return the same root to root_tol. */
+enum { ESRK_ROOT_ILLINOIS = 0, ESRK_ROOT_BRENT = 1, ESRK_ROOT_BISECTION = 2 };
 /* Relaxation applied by esrk_step (esrk_set_relaxation_mode). */
 enum { ESRK_RELAX_LOCAL = 0, ESRK_RELAX_GLOBAL = 1, ESRK_RELAX_NONE = 2 };
 
@@ -231,6 +235,15 @@ esrk_status esrk_set_adaptive(esrk_ctx* ctx, double atol, double rtol);
  * (EINVAL if none are set).  ESRK_ENOTSUP for a method without an embedded
  * pair.  Enqueue only. */
 esrk_status esrk_error_estimate(esrk_ctx* ctx, double* err, double* norm, void* stream);
+
+/* Root-solve method of the local relaxation (Sec. 4 names Brent's method and
+ * the first method of Alefeld, Potra and Shi as robust, secant and Newton as
+ * slightly faster): ESRK_ROOT_ILLINOIS (default: regula falsi with the
+ * Illinois modification), ESRK_ROOT_BRENT (Brent's inverse quadratic
+ * interpolation / secant / bisection safeguards; not with a network's first
+ * trial point, which keeps the Illinois rule) or ESRK_ROOT_BISECTION.
+ * EINVAL for another value. */
+esrk_status esrk_set_root_method(esrk_ctx* ctx, int method);
 
 /* Synchronizes `ctx`'s work on the stream of its last call, returns and clears
  * the latched device status; *bad_elem (nullable) receives the smallest

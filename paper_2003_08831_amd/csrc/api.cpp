@@ -51,6 +51,7 @@ struct esrk_ctx {
   const float* step_model = nullptr;  // network used by esrk_step for first trial points
   float* step_feats = nullptr;        // raw features written by esrk_step (nullable)
   int relax_mode = ESRK_RELAX_LOCAL;  // relaxation used by esrk_step
+  int root_method = ESRK_ROOT_ILLINOIS;
   double* glob_parts = nullptr;       // global relaxation: block partials
   double* glob_out = nullptr;         // global relaxation: reduced sums
   hipStream_t last = nullptr;
@@ -574,6 +575,7 @@ static esrk::RelaxArgs relax_args(esrk_ctx* x, const double* u_old, const double
   r.tol = x->cfg.root_tol;
   r.gamma_max = x->cfg.gamma_max;
   r.maxit = x->cfg.root_maxit;
+  r.method = x->root_method;
   r.fp32_increments = x->cfg.precision == ESRK_FP32_FLUX;
   return r;
 }
@@ -712,6 +714,14 @@ esrk_status esrk_error_estimate(esrk_ctx* x, double* err, double* norm, void* st
     e = esrk::launch_adapt(x->errk, (int)x->ne, (double)(x->N * x->nv), x->order_emb, 0,
                            x->scal, norm, s);
   return hip_status(e);
+}
+
+esrk_status esrk_set_root_method(esrk_ctx* x, int method) {
+  if (!x || (method != ESRK_ROOT_ILLINOIS && method != ESRK_ROOT_BRENT &&
+             method != ESRK_ROOT_BISECTION))
+    return ESRK_EINVAL;
+  x->root_method = method;
+  return ESRK_OK;
 }
 
 esrk_status esrk_set_relaxation_mode(esrk_ctx* x, int mode) {

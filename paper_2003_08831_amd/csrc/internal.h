@@ -177,6 +177,7 @@ struct RelaxArgs {
   DevScalars* scal;
   double tol, gamma_max;
   int maxit;
+  int method;  // ESRK_ROOT_*: trial-point rule inside the bracket
   // FP32-flux increments: an element whose phi(0) >= 0 while its entropy
   // change r(1) stays within the FP32 rounding level is inactive, not ENOROOT
   int fp32_increments;

@@ -157,7 +157,7 @@ struct RelaxCfg {
 
 // One block's work: EPB elements starting at element kb of the mesh md; the
 // block partial goes to a.parts[part].
-template <int DIM, int N, bool NET>
+template <int DIM, int N, bool NET, bool BRENT = false>
 __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims& md,
                                             const RelaxArgs& a, const int kb, const int part,
                                             const long long elem_base) {
@@ -325,6 +325,12 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
   double lo = 0.0, flo = phi0, hi = 1.0, fhi = 0.0, gk = 1.0, g_trial = 1.0;
   bool hi_known = false, done = !valid;
   int side = 0, its = 0;
+  // Brent's method (own instantiation: its state costs registers): previous
+  // iterate (ba, fba), last and second-to-last steps
+  double ba = NAN, fba = NAN, bd = 0.0, be = 0.0;
+  const int method = BRENT ? ESRK_ROOT_BRENT
+                           : (a.method == ESRK_ROOT_BISECTION ? ESRK_ROOT_BISECTION
+                                                             : ESRK_ROOT_ILLINOIS);
   const bool have_guess = a.guess != nullptr;
   double dtf = 0.0;
   if (want_feats) dtf = a.dt_dev ? *a.dt_dev : a.dt_host;
@@ -376,13 +382,15 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
         continue;
       }
     }
+    // Illinois: a bracket end kept twice in a row has its value halved
+    const bool illinois = method == ESRK_ROOT_ILLINOIS;
     if (f <= 0.0) {
-      if (hi_known && side == -1) fhi *= 0.5;
+      if (illinois && hi_known && side == -1) fhi *= 0.5;
       lo = g_trial;
       flo = f;
       side = -1;
     } else {
-      if (hi_known && side == +1) flo *= 0.5;
+      if (illinois && hi_known && side == +1) flo *= 0.5;
       hi = g_trial;
       fhi = f;
       hi_known = true;
@@ -414,8 +422,53 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
     double g;
     if (g0 > 0.0) {
       g = g0;
-    } else if (isinf(fhi)) {
+    } else if (method == ESRK_ROOT_BISECTION || isinf(fhi)) {
       g = 0.5 * (lo + hi);
+    } else if (BRENT) {
+      // Brent's step from the better bracket end b towards the other end c:
+      // inverse quadratic interpolation through (a, b, c), a the previous b,
+      // when the three values differ, else the secant through (a, b); taken
+      // only while the steps shrink faster than bisection's, else bisection
+      const bool lo_best = fabs(flo) <= fabs(fhi);
+      const double b = lo_best ? lo : hi, fb = lo_best ? flo : fhi;
+      const double c = lo_best ? hi : lo, fc = lo_best ? fhi : flo;
+      // a: the previous b if the newest point became b, else the newest point
+      double pa = (g_trial == b) ? ba : g_trial, fpa = (g_trial == b) ? fba : f;
+      if (!(pa == pa)) {
+        // first Brent step: a = c and the last steps as wide as the bracket
+        pa = c;
+        fpa = fc;
+        bd = be = c - b;
+      }
+      const double m = 0.5 * (c - b);
+      const double tolb = 0.25 * tw;
+      double step = m;
+      if (fabs(be) >= tolb && fabs(fpa) > fabs(fb) && isfinite(fpa)) {
+        const double s = fb / fpa;
+        double p, q;
+        if (pa == c || fpa == fc) {
+          p = 2.0 * m * s;
+          q = 1.0 - s;
+        } else {
+          const double qq = fpa / fc, rr = fb / fc;
+          p = s * (2.0 * m * qq * (qq - rr) - (b - pa) * (rr - 1.0));
+          q = (qq - 1.0) * (rr - 1.0) * (s - 1.0);
+        }
+        if (p > 0.0) q = -q;
+        else p = -p;
+        if (2.0 * p < fmin(3.0 * m * q - fabs(tolb * q), fabs(be * q))) {
+          be = bd;
+          step = p / q;
+        } else {
+          be = m;
+        }
+      } else {
+        be = m;
+      }
+      bd = step;
+      ba = b;
+      fba = fb;
+      g = b + (fabs(step) > tolb ? step : copysign(tolb, m));
     } else {
       g = lo - flo * (hi - lo) / (fhi - flo);
     }
@@ -482,6 +535,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
   const MeshDims md = dims_of(mp);
   relax_block<DIM, N, NET>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB, blockIdx.x, 0);
 }
+// Brent's trial points (no network guess on this path).
+template <int DIM, int N>
+__global__ void __launch_bounds__(256) relax_kernel_brent(const MeshParams mp, const RelaxArgs a) {
+  const MeshDims md = dims_of(mp);
+  relax_block<DIM, N, false, true>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB, blockIdx.x, 0);
+}
 
 // Batched form over (simulation, first element) items; partial per item.
 template <int DIM, int N>
@@ -542,6 +601,8 @@ static hipError_t relax_one(const MeshParams& mp, const RelaxArgs& a, hipStream_
   const int blocks = (mp.ne + C::EPB - 1) / C::EPB;
   if (a.model || a.feats)
     hipLaunchKernelGGL((relax_kernel<DIM, N, true>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
+  else if (a.method == ESRK_ROOT_BRENT)
+    hipLaunchKernelGGL((relax_kernel_brent<DIM, N>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
   else if constexpr (DIM == 3 && C::NPL == 1)
     hipLaunchKernelGGL((relax_kernel_w4<DIM, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, mp,
                        a);

@@ -19,6 +19,7 @@ FP64, FP32_FLUX = 0, 1
 MLP_TRAINED, MLP_MODEL, MLP_IN = 1281, 1298, 5
 SSPRK33, RK44, BSRK43, BSRK85 = 0, 1, 2, 3
 RELAX_LOCAL, RELAX_GLOBAL, RELAX_NONE = 0, 1, 2
+ROOT_ILLINOIS, ROOT_BRENT, ROOT_BISECTION = 0, 1, 2
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "EHIP", 3: "ENOMEM", 4: "ENOROOT", 5: "ENONPHYS",
           6: "ENAN", 7: "ENOTSUP"}
@@ -87,6 +88,8 @@ def load():
     L.esrk_stage_phi0.restype = st
     L.esrk_local_relaxation_solve_phi0.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.esrk_local_relaxation_solve_phi0.restype = st
+    L.esrk_set_root_method.argtypes = [vp, C.c_int]
+    L.esrk_set_root_method.restype = st
     L.esrk_set_adaptive.argtypes = [vp, dp, dp]
     L.esrk_set_adaptive.restype = st
     L.esrk_error_estimate.argtypes = [vp, vp, vp, vp]
@@ -242,6 +245,9 @@ class Context:
         _check(load().esrk_local_relaxation_solve_phi0(
             self._h, _ptr(u_old), _ptr(du), _ptr(deta), _ptr(phi0), _ptr(gamma_k), _ptr(gamma),
             _ptr(iters), _stream(stream)), "esrk_local_relaxation_solve_phi0")
+
+    def set_root_method(self, method):
+        _check(load().esrk_set_root_method(self._h, int(method)), "esrk_set_root_method")
 
     def set_adaptive(self, atol, rtol):
         _check(load().esrk_set_adaptive(self._h, float(atol), float(rtol)), "esrk_set_adaptive")

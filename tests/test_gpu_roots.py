@@ -1,0 +1,65 @@
+"""GPU relaxation root solves with each trial-point rule (Illinois regula
+falsi, Brent, bisection) against the oracle's bisection on the same
+increments; the iteration counts are printed for the comparison the paper
+makes between robust and fast root solvers."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_2003_08831_amd import esrk  # noqa: E402
+from tests.gpu_helpers import ctx_for, dev, host, zeros  # noqa: E402
+from tests.oracle_helpers import orc_mesh  # noqa: E402
+from tests.test_gpu_parity import CASES, check_gammas, make_state  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+METHODS = [(esrk.ROOT_ILLINOIS, "illinois"), (esrk.ROOT_BRENT, "brent"),
+           (esrk.ROOT_BISECTION, "bisection")]
+
+
+@pytest.mark.parametrize("name,ms,kind", [CASES[0], CASES[2], CASES[4], CASES[7], CASES[9]],
+                         ids=["d1p3", "d2p3_vortex", "d2p4", "d3p3_tgv", "d3p4"])
+def test_root_methods_match_oracle(name, ms, kind):
+    u = make_state(ms, kind, seed=7)
+    m = orc_mesh(O, ms)
+    du, deta = O.rk_step(m, O.RK44, u, O.cfl_dt(m, u, 0.5))
+    ref = O.local_relaxation_solve(m, u, du, deta)
+    assert ref["rc"] == 0
+    ctx = ctx_for(ms, tableau=esrk.RK44)
+    counts = {}
+    for method, label in METHODS:
+        ctx.set_root_method(method)
+        gk, gam = zeros(ctx.ne), zeros(1)
+        iters = torch.zeros(ctx.ne, dtype=torch.int32, device="cuda")
+        ctx.local_relaxation_solve(dev(u), dev(du), dev(deta), gk, gam, iters=iters)
+        check_gammas(host(gk), ref)
+        it = host(iters)
+        act = np.isfinite(ref["gamma_k"])
+        counts[label] = (it[act].mean() if act.any() else 0.0, it.max())
+        assert it.max() <= (60 if method == esrk.ROOT_BISECTION else 20), label
+    print(f"[root methods {name}] mean/max phi evaluations per active element: " + ", ".join(
+        f"{k} {v[0]:.2f}/{v[1]}" for k, v in counts.items()))
+    assert ctx.sync_status()[0] == 0
+    with pytest.raises(esrk.EsrkError):
+        ctx.set_root_method(9)
+
+
+def test_root_methods_in_steps():
+    """Whole relaxed steps with each rule give the same states to the root
+    tolerance's effect (gamma within 1e-11, states within 1e-11 |du|)."""
+    ms = CASES[7][1]
+    u0 = make_state(ms, "tgv")
+    outs = []
+    for method, _ in METHODS:
+        ctx = ctx_for(ms, tableau=esrk.RK44)
+        ctx.set_root_method(method)
+        ud, t, st = dev(u0), zeros(1), zeros(8)
+        for _ in range(3):
+            ctx.step(ud, t, 0.0, None, st)
+        assert ctx.sync_status()[0] == 0
+        outs.append((host(ud), host(st)))
+    for u, st in outs[1:]:
+        assert abs(st[0] - outs[0][1][0]) <= 1e-11
+        assert np.abs(u - outs[0][0]).max() <= 1e-10 * np.abs(outs[0][0]).max()
