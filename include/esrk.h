@@ -139,8 +139,13 @@ esrk_status esrk_rk_stage(esrk_ctx* ctx, int stage, double dt, const double* u_o
  * 64 eps (sum_i M_i sum_v |w_v du_v| + |deta_k|)) get +INF.  With precision
  * ESRK_FP32_FLUX the increments carry FP32 flux rounding: eps is then the
  * FP32 epsilon, and an element with phi_k(0) >= 0 whose entropy change r_k(1)
- * stays within that level is inactive too.  Any other element with
- * phi_k(0) >= 0 latches ESRK_ENOROOT.  *gamma (device scalar) =
+ * stays within that level is inactive too.  An element with
+ * -B_k(1)/2 < phi_k(0) <= its round-off level (B_k(1) = r_k(1) - phi_k(0),
+ * the relative entropy of the step; the root would lie below about 1/2) is
+ * degenerate and inactive: the existence lemma needs the element's own slope
+ * at u_old to carry the curvature, and an element that a wave reaches only
+ * in the last stages of the step has none.  An element with phi_k(0) above
+ * the round-off level latches ESRK_ENOROOT.  *gamma (device scalar) =
  * min_k gamma_k, or 1 if every element is inactive.  gamma_guess (nullable,
  * float [num_elems]) seeds the solve: after phi_k(1) it is the next trial
  * point if it lies in (0, gamma_max]; the result does not depend on it beyond
@@ -235,6 +240,16 @@ esrk_status esrk_set_adaptive(esrk_ctx* ctx, double atol, double rtol);
  * (EINVAL if none are set).  ESRK_ENOTSUP for a method without an embedded
  * pair.  Enqueue only. */
 esrk_status esrk_error_estimate(esrk_ctx* ctx, double* err, double* norm, void* stream);
+
+/* Dirichlet boundaries for a 1-D Euler context (Sec. 4's shock tube, sine-shock
+ * and local-gamma problems are posed on intervals): u_left and u_right (host,
+ * 3 conserved values each) are the exterior states that enter the first and
+ * last element's outer faces through the same interface flux as interior
+ * faces.  Both NULL: periodic again (default).  ENOTSUP for dim != 1 or a
+ * Navier-Stokes context, ENONPHYS for a state with rho <= 0 or p <= 0,
+ * EINVAL for one NULL pointer or non-finite values.  Applies to the calls
+ * that follow. */
+esrk_status esrk_set_dirichlet(esrk_ctx* ctx, const double* u_left, const double* u_right);
 
 /* Root-solve method of the local relaxation (Sec. 4 names Brent's method and
  * the first method of Alefeld, Potra and Shi as robust, secant and Newton as

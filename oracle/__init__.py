@@ -39,6 +39,8 @@ class Mesh(C.Structure):
         ("prandtl", C.c_double),
         ("lambda_scale", C.c_double),
         ("volume_flux", C.c_int),
+        ("bc", C.c_int),
+        ("ubc", C.c_double * 10),
     ]
 
 
@@ -128,7 +130,9 @@ def _p(a):
 
 
 def mesh(dim, deg, nel, lo, hi, gas_gamma=1.4, gas_r=1.0, mu=0.0, prandtl=0.72,
-         lambda_scale=1.0, volume_flux=0) -> Mesh:
+         lambda_scale=1.0, volume_flux=0, dirichlet=None) -> Mesh:
+    """dirichlet = (u_left, u_right) conserved exterior states (1-D): Dirichlet
+    boundaries at both ends instead of periodic ones."""
     m = Mesh()
     m.dim, m.deg = dim, deg
     nel = list(nel) + [1] * (3 - len(nel))
@@ -138,6 +142,13 @@ def mesh(dim, deg, nel, lo, hi, gas_gamma=1.4, gas_r=1.0, mu=0.0, prandtl=0.72,
         m.nel[q], m.lo[q], m.hi[q] = nel[q], lo[q], hi[q]
     m.gas_gamma, m.gas_r, m.mu, m.prandtl = gas_gamma, gas_r, mu, prandtl
     m.lambda_scale, m.volume_flux = lambda_scale, volume_flux
+    m.bc = 0
+    if dirichlet is not None:
+        m.bc = 1
+        for s in range(2):
+            st = list(dirichlet[s]) + [0.0] * (5 - len(dirichlet[s]))
+            for v in range(5):
+                m.ubc[5 * s + v] = float(st[v])
     return m
 
 

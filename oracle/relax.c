@@ -225,12 +225,18 @@ int orc_local_relaxation_solve_a(const orc_mesh* g, const orc_relax_opts* o,
     int its = 0;
     if (curv <= noise) {
       gk = INFINITY; /* inactive: no determinable root */
-    } else if (!(phi0 < 0.0)) {
+    } else if (phi0 > noise) {
       gk = 0.0;
       if (rc == ORC_OK) {
         rc = ORC_ENOROOT;
         if (bad_elem) *bad_elem = k;
       }
+    } else if (phi0 > -0.5 * curv) {
+      /* degenerate: phi(0) ~ 0 while the relative entropy is not, so the
+       * root lies below about 1/2 (the existence lemma needs the element's
+       * own slope at u_old to carry the curvature; an element that a wave
+       * reaches only in the last stages of the step has none) */
+      gk = INFINITY;
     } else {
       orc_root_nondecreasing(phi_elem, &c, phi0, o, &gk, &its);
     }

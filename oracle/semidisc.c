@@ -1,5 +1,7 @@
 /*
- * Entropy-stable semidiscretization on a periodic Cartesian mesh of
+ * Entropy-stable semidiscretization on a periodic Cartesian mesh (or a 1-D
+ * mesh with Dirichlet exterior states at both ends, entering through the
+ * same interface flux) of
  * tensor-product Lobatto elements (Sec. 3.1, the element equation: the
  * flux-differencing volume term 2 D o F(q,q) 1, interface SATs with added
  * interface dissipation, and the BR1-type viscous terms).
@@ -31,7 +33,7 @@
 #include "esrk_oracle.h"
 
 typedef struct {
-  int dim, n, nv, nd;
+  int dim, n, nv, nd, bc;
   long ne, N;
   int nel[3];
   double h[3];
@@ -40,6 +42,9 @@ typedef struct {
 
 static int setup(const orc_mesh* g, geom* G) {
   if (g->dim < 1 || g->dim > 3 || g->deg < 1 || g->deg > 15) return ORC_EINVAL;
+  /* Dirichlet boundaries: 1-D Euler only */
+  if (g->bc != 0 && (g->bc != 1 || g->dim != 1 || g->mu > 0.0)) return ORC_EINVAL;
+  G->bc = g->bc;
   G->dim = g->dim;
   G->n = g->deg + 1;
   G->nv = g->dim + 2;
@@ -77,9 +82,12 @@ static void elem_index(const geom* G, long k, int* km) {
 static long elem_flat(const geom* G, const int* km) {
   return km[0] + (long)G->nel[0] * (km[1] + (long)G->nel[1] * km[2]);
 }
+/* Neighbour element across the face of k in direction m (dir = -1 or +1);
+ * -1 on a Dirichlet boundary. */
 static long neighbour(const geom* G, long k, int m, int dir) {
   int km[3];
   elem_index(G, k, km);
+  if (G->bc && (km[m] + dir < 0 || km[m] + dir >= G->nel[m])) return -1;
   km[m] = (km[m] + dir + G->nel[m]) % G->nel[m];
   return elem_flat(G, km);
 }
@@ -178,7 +186,10 @@ static void surface_term(const orc_mesh* g, const geom* G, const double* u, doub
       for (int m = 0; m < G->dim; ++m) {
         if (im[m] == p) { /* this node is the left state of the +m interface */
           long kn = neighbour(G, k, m, +1);
-          gather(G, u, kn * G->nd + node_with(G, i, m, 0), un);
+          if (kn < 0)
+            for (int v = 0; v < G->nv; ++v) un[v] = g->ubc[1][v]; /* right boundary */
+          else
+            gather(G, u, kn * G->nd + node_with(G, i, m, 0), un);
           interface_flux(g, m, ui, un, fs);
           orc_phys_flux(G->dim, g->gas_gamma, m, ui, fp);
           double c = (2.0 / G->h[m]) / G->w[p];
@@ -186,7 +197,10 @@ static void surface_term(const orc_mesh* g, const geom* G, const double* u, doub
         }
         if (im[m] == 0) { /* right state of the -m interface */
           long kn = neighbour(G, k, m, -1);
-          gather(G, u, kn * G->nd + node_with(G, i, m, p), un);
+          if (kn < 0)
+            for (int v = 0; v < G->nv; ++v) un[v] = g->ubc[0][v]; /* left boundary */
+          else
+            gather(G, u, kn * G->nd + node_with(G, i, m, p), un);
           interface_flux(g, m, un, ui, fs);
           orc_phys_flux(G->dim, g->gas_gamma, m, ui, fp);
           double c = (2.0 / G->h[m]) / G->w[0];
@@ -212,6 +226,7 @@ double orc_interface_dissipation(const orc_mesh* g, const double* u) {
         double uL[5], uR[5], wL[5], wR[5];
         gather(&G, u, k * G.nd + i, uL);
         long kn = neighbour(&G, k, m, +1);
+        if (kn < 0) continue; /* interior interfaces only */
         gather(&G, u, kn * G.nd + node_with(&G, i, m, 0), uR);
         orc_entropy_vars(G.dim, g->gas_gamma, uL, wL);
         orc_entropy_vars(G.dim, g->gas_gamma, uR, wR);

@@ -716,6 +716,27 @@ esrk_status esrk_error_estimate(esrk_ctx* x, double* err, double* norm, void* st
   return hip_status(e);
 }
 
+esrk_status esrk_set_dirichlet(esrk_ctx* x, const double* u_left, const double* u_right) {
+  if (!x || (!u_left) != (!u_right)) return ESRK_EINVAL;
+  if (!u_left) {
+    x->mp.bc = 0;
+    return ESRK_OK;
+  }
+  if (x->cfg.dim != 1 || x->cfg.mu > 0.0) return ESRK_ENOTSUP;
+  for (int v = 0; v < 3; ++v) {
+    if (!std::isfinite(u_left[v]) || !std::isfinite(u_right[v])) return ESRK_EINVAL;
+    x->mp.ubc[0][v] = u_left[v];
+    x->mp.ubc[1][v] = u_right[v];
+  }
+  const double g1 = x->cfg.gas_gamma - 1.0;
+  for (int s = 0; s < 2; ++s) {
+    const double* q = x->mp.ubc[s];
+    if (!(q[0] > 0.0) || !(g1 * (q[2] - 0.5 * q[1] * q[1] / q[0]) > 0.0)) return ESRK_ENONPHYS;
+  }
+  x->mp.bc = 1;
+  return ESRK_OK;
+}
+
 esrk_status esrk_set_root_method(esrk_ctx* x, int method) {
   if (!x || (method != ESRK_ROOT_ILLINOIS && method != ESRK_ROOT_BRENT &&
              method != ESRK_ROOT_BISECTION))

@@ -368,10 +368,14 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
         done = true;
         continue;
       }
-      if (!(phi0 < 0.0)) {
-        // with FP32-flux increments the estimate carries FP32 rounding: an
-        // entropy change r(1) within that level leaves gamma undetermined
-        if (a.fp32_increments && ok && phi0 + q <= noise) {
+      if (!(phi0 <= -0.5 * q)) {
+        // phi(0) ~ 0 against the relative entropy (root below about 1/2:
+        // an element reached by a wave only in the last stages of the step
+        // has no slope of its own at u_old) or, with FP32-flux increments,
+        // an entropy change r(1) within the FP32 rounding level: no
+        // determinable root, inactive.  phi(0) above its round-off level:
+        // no positive root, an error.
+        if (phi0 <= noise || (a.fp32_increments && ok && phi0 + q <= noise)) {
           gk = INFINITY;
           done = true;
           continue;

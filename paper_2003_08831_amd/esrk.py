@@ -88,6 +88,8 @@ def load():
     L.esrk_stage_phi0.restype = st
     L.esrk_local_relaxation_solve_phi0.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.esrk_local_relaxation_solve_phi0.restype = st
+    L.esrk_set_dirichlet.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.esrk_set_dirichlet.restype = st
     L.esrk_set_root_method.argtypes = [vp, C.c_int]
     L.esrk_set_root_method.restype = st
     L.esrk_set_adaptive.argtypes = [vp, dp, dp]
@@ -245,6 +247,15 @@ class Context:
         _check(load().esrk_local_relaxation_solve_phi0(
             self._h, _ptr(u_old), _ptr(du), _ptr(deta), _ptr(phi0), _ptr(gamma_k), _ptr(gamma),
             _ptr(iters), _stream(stream)), "esrk_local_relaxation_solve_phi0")
+
+    def set_dirichlet(self, u_left=None, u_right=None):
+        """Exterior conserved states (3 values each, host) of a 1-D context;
+        None for both: periodic."""
+        def arr(x):
+            if x is None:
+                return None
+            return (C.c_double * 3)(*[float(v) for v in x])
+        _check(load().esrk_set_dirichlet(self._h, arr(u_left), arr(u_right)), "esrk_set_dirichlet")
 
     def set_root_method(self, method):
         _check(load().esrk_set_root_method(self._h, int(method)), "esrk_set_root_method")

@@ -201,6 +201,45 @@ def local_gamma_1d_state(ms: MeshSpec) -> np.ndarray:
     return conserved(1, ms.gas_gamma, rho, [v], p).reshape(-1).copy()
 
 
+# ------------------------------------------- 1-D problems with boundaries ----
+def sod_mesh(nel: int = 128, deg: int = 3) -> MeshSpec:
+    return MeshSpec(dim=1, deg=deg, nel=(nel, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                    meta=dict(name="sod_shock_tube"))
+
+
+def sod_state(ms: MeshSpec) -> np.ndarray:
+    """(rho, v, p) = (1, 0, 1) for x < 1/2, (1/8, 0, 1/10) for x >= 1/2."""
+    (x,) = node_coords(ms)[:1]
+    left = x < 0.5
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    return conserved(1, ms.gas_gamma, rho, [np.zeros_like(x)], p).reshape(-1).copy()
+
+
+def shock_sine_mesh(nel: int = 256, deg: int = 3) -> MeshSpec:
+    return MeshSpec(dim=1, deg=deg, nel=(nel, 1, 1), lo=(-5.0, 0.0, 0.0), hi=(5.0, 1.0, 1.0),
+                    meta=dict(name="sine_shock_interaction"))
+
+
+def shock_sine_state(ms: MeshSpec) -> np.ndarray:
+    """(rho, v, p) = (1.515695, 0.523346, 1.805) for x < -4.5, else
+    (1 + 0.1 sin(20 pi x), 0, 1)."""
+    (x,) = node_coords(ms)[:1]
+    left = x < -4.5
+    rho = np.where(left, 1.515695, 1.0 + 0.1 * np.sin(20.0 * math.pi * x))
+    v = np.where(left, 0.523346, 0.0)
+    p = np.where(left, 1.805, 1.0)
+    return conserved(1, ms.gas_gamma, rho, [v], p).reshape(-1).copy()
+
+
+def end_states(ms: MeshSpec, u: np.ndarray):
+    """Conserved states at the first and the last node of a 1-D mesh (the
+    Lobatto nodes include the interval's ends): the Dirichlet exterior
+    states that hold the initial boundary values."""
+    U = np.asarray(u).reshape(ms.nv, -1)
+    return U[:, 0].copy(), U[:, -1].copy()
+
+
 # ------------------------------------------------------------ random states ----
 def random_state(ms: MeshSpec, seed: int = 0, rel: float = 0.2, vmax: float = 0.5,
                  smooth: bool = False) -> np.ndarray:

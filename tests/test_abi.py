@@ -102,5 +102,6 @@ def test_error_control_entry_point_validation():
     assert L.esrk_error_estimate(None, None, None, None) == 1
     assert L.esrk_stage_phi0(None, None, None) == 1
     assert L.esrk_set_root_method(None, esrk.ROOT_BRENT) == 1
+    assert L.esrk_set_dirichlet(None, None, None) == 1
     assert L.esrk_local_relaxation_solve_phi0(None, None, None, None, None, None, None, None,
                                               None) == 1
