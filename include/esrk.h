@@ -199,22 +199,23 @@ esrk_status esrk_step(esrk_ctx* ctx, double* u, double* t, double dt, double* ga
  * curvature r(1) - phi(0) is at most
  * 64 eps (sum_i M_i sum_v |w_v du_v| + sum_k |deta_k|); otherwise
  * phi(0) >= 0 returns ESRK_ENOROOT.  The root lies between the smallest and
- * the largest per-element root.  The bracket logic runs on the host between
- * device passes (each pass sweeps the nodes once for four trial values and
- * synchronizes the stream), so this call blocks; *gamma (device scalar) is
- * written before it returns, *passes (nullable, host) receives the number of
- * passes.  ESRK_ENAN if the sums at gamma = 1 are not finite (a state that is
- * not physical, say); nothing is latched on the device. */
+ * the largest per-element root.  Each device pass sweeps the nodes once for
+ * four trial values and a one-block kernel updates the bracket on the device
+ * (up to 12 passes; a pass after convergence returns at once).  This call
+ * waits for the result: *gamma (device scalar) is written before it returns,
+ * *passes (nullable, host) receives the number of passes that did work.
+ * ESRK_ENAN if the sums at gamma = 1 are not finite (a state that is not
+ * physical, say); nothing is latched on the device. */
 esrk_status esrk_global_relaxation_solve(esrk_ctx* ctx, const double* u_old,
                                          const double* du, const double* deta,
                                          double* gamma, int* passes, void* stream);
 
 /* Relaxation used by esrk_step: ESRK_RELAX_LOCAL (default: gamma = min_k
- * gamma_k, enqueue-only), ESRK_RELAX_GLOBAL (the root of
- * esrk_global_relaxation_solve; the step then synchronizes its stream once
- * per bracket pass, returns a status latched by its stages at once, and
- * gamma_k_out is not written) or ESRK_RELAX_NONE (the
- * unrelaxed Runge-Kutta step, gamma = 1).  In the last two modes stats_out
+ * gamma_k), ESRK_RELAX_GLOBAL (the root of esrk_global_relaxation_solve,
+ * found on the device without host synchronization; ESRK_ENOROOT and
+ * ESRK_ENAN are latched like the local solve's errors, gamma_k_out is not
+ * written) or ESRK_RELAX_NONE (the unrelaxed Runge-Kutta step, gamma = 1).
+ * All three are enqueue-only.  In the last two modes stats_out
  * reports zero inactive elements and zero evaluations.  EINVAL for another
  * mode. */
 esrk_status esrk_set_relaxation_mode(esrk_ctx* ctx, int mode);

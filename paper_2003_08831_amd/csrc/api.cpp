@@ -53,7 +53,7 @@ struct esrk_ctx {
   int relax_mode = ESRK_RELAX_LOCAL;  // relaxation used by esrk_step
   int root_method = ESRK_ROOT_ILLINOIS;
   double* glob_parts = nullptr;       // global relaxation: block partials
-  double* glob_out = nullptr;         // global relaxation: reduced sums
+  esrk::GlobState* glob_state = nullptr;  // global relaxation: bracket and result
   hipStream_t last = nullptr;
 };
 
@@ -221,130 +221,9 @@ void stage_extras(const esrk_ctx* x, int stage, bool with_err, esrk::RhsArgs& a)
   a.ex = x->ex_dev ? x->ex_dev + (with_err ? esrk::kMaxStages : 0) + stage : nullptr;
 }
 
-// Global relaxation (one gamma with eta(u_old + gamma du) = eta(u_old) +
-// gamma sum_k deta_k): the bracket logic runs here on the host, each pass
-// evaluates kGlobTrials trial values on the device in one sweep over the
-// nodes and reads back the kGlobParts sums (one stream synchronization per
-// pass).  Same rules as the per-element solve: inactive (gamma = 1) when the
-// curvature is at the round-off level, ESRK_ENOROOT when phi(0) >= 0, bracket
-// [0, 1] doubled up to gamma_max, then regula-falsi-centred trial points until
-// the bracket is narrower than root_tol * max(1, gamma); the lower end is
-// returned.
-// With check_latched, a status latched on the device by the kernels before
-// the solve (a non-physical stage state, say) is returned as it is and stays
-// latched.
-esrk_status global_solve(esrk_ctx* x, const double* u_old, const double* du, const double* deta,
-                         const double* phi0_in, double* gamma_host, int* passes_out,
-                         bool check_latched, bool check_reject, hipStream_t s) {
-  double o[esrk::kGlobParts];
-  int passes = 0, latched = 0, rejected = 0;
-  auto eval = [&](int first, const esrk::GlobTrials& t) -> bool {
-    ++passes;
-    if (esrk::launch_glob_eval(x->mp, u_old, du, deta, phi0_in, first, t, x->glob_parts,
-                               x->glob_out,
-                               s) != hipSuccess)
-      return false;
-    if (hipMemcpyAsync(o, x->glob_out, sizeof(o), hipMemcpyDeviceToHost, s) != hipSuccess)
-      return false;
-    if (first && check_latched &&
-        hipMemcpyAsync(&latched, &x->scal->status, sizeof(int), hipMemcpyDeviceToHost, s) !=
-            hipSuccess)
-      return false;
-    if (first && check_reject &&
-        hipMemcpyAsync(&rejected, &x->scal->rejected, sizeof(int), hipMemcpyDeviceToHost, s) !=
-            hipSuccess)
-      return false;
-    return hipStreamSynchronize(s) == hipSuccess;
-  };
-  esrk::GlobTrials t;
-  for (int j = 0; j < esrk::kGlobTrials; ++j) t.g[j] = 1.0;
-  if (!eval(1, t)) return ESRK_EHIP;
-  if (latched != 0) return (esrk_status)latched;
-  if (rejected) {
-    *gamma_host = INFINITY;  // a rejected attempt: the update is skipped anyway
-    if (passes_out) *passes_out = passes;
-    return ESRK_OK;
-  }
-  if (!std::isfinite(o[0]) || !std::isfinite(o[1]) || !std::isfinite(o[3])) return ESRK_ENAN;
-  const double phi0 = o[0] - o[2];
-  const double noise = 64.0 * DBL_EPSILON * (o[1] + o[3]);
-  const double B1 = o[4];
-  const double tol = x->cfg.root_tol, gmax = x->cfg.gamma_max;
-  if (passes_out) *passes_out = passes;
-  if (std::isfinite(B1) && B1 <= noise) {
-    *gamma_host = 1.0;
-    return ESRK_OK;
-  }
-  if (!(phi0 < 0.0)) return ESRK_ENOROOT;
-  auto phi_at = [&](double g, double Bg) { return std::isfinite(Bg) ? phi0 + Bg / g : INFINITY; };
-  double lo = 0.0, flo = phi0, hi = 1.0, fhi = phi_at(1.0, B1);
-  if (!(fhi > 0.0)) {
-    // expand: 2, 4, 8, ... up to gamma_max
-    lo = 1.0;
-    flo = fhi;
-    bool found = false;
-    while (!found && lo < gmax) {
-      for (int j = 0; j < esrk::kGlobTrials; ++j) t.g[j] = std::fmin(lo * std::ldexp(1.0, j + 1), gmax);
-      if (!eval(0, t)) return ESRK_EHIP;
-      for (int j = 0; j < esrk::kGlobTrials && !found; ++j) {
-        const double f = phi_at(t.g[j], o[4 + j]);
-        if (f > 0.0) {
-          hi = t.g[j];
-          fhi = f;
-          found = true;
-        } else {
-          lo = t.g[j];
-          flo = f;
-        }
-      }
-    }
-    if (!found) {
-      *gamma_host = gmax;
-      if (passes_out) *passes_out = passes;
-      return ESRK_OK;
-    }
-  }
-  double s_prev = NAN;
-  bool halved = true;
-  for (int pass = 0; pass < x->cfg.root_maxit; ++pass) {
-    const double tw = tol * std::fmax(1.0, hi);
-    const double width = hi - lo;
-    if (width <= tw) break;
-    if (halved) {
-      double c = std::isinf(fhi) ? 0.5 * (lo + hi) : lo - flo * width / (fhi - flo);
-      if (!(c == c)) c = 0.5 * (lo + hi);
-      c = std::fmin(std::fmax(c, lo + 0.25 * tw), hi - 0.25 * tw);
-      double w = std::isnan(s_prev) ? 1e-3 * width : 2.0 * std::fabs(c - s_prev);
-      w = std::fmax(w, 0.25 * tw);
-      for (int j = 0; j < esrk::kGlobTrials; ++j) {
-        const double g = c + (j - 0.5 * (esrk::kGlobTrials - 1)) * w;
-        t.g[j] = std::fmin(std::fmax(g, lo + 0.125 * tw), hi - 0.125 * tw);
-      }
-      s_prev = c;
-    } else {
-      // the last pass did not halve the bracket: evenly spaced points
-      for (int j = 0; j < esrk::kGlobTrials; ++j)
-        t.g[j] = lo + (j + 1) * width / (esrk::kGlobTrials + 1);
-    }
-    if (!eval(0, t)) return ESRK_EHIP;
-    for (int j = 0; j < esrk::kGlobTrials; ++j) {
-      const double f = phi_at(t.g[j], o[4 + j]);
-      if (f <= 0.0) {
-        if (t.g[j] > lo) {
-          lo = t.g[j];
-          flo = f;
-        }
-      } else if (t.g[j] < hi) {
-        hi = t.g[j];
-        fhi = f;
-      }
-    }
-    halved = (hi - lo) <= 0.5 * width;
-  }
-  *gamma_host = lo;
-  if (passes_out) *passes_out = passes;
-  return ESRK_OK;
-}
+// Sweeps of the device-driven global relaxation solve (a converged solve
+// makes the remaining sweeps return at once).
+constexpr int kGlobMaxPasses = 12;
 
 }  // namespace
 
@@ -448,7 +327,7 @@ esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
   ok = ok &&
        hipMalloc(&x->glob_parts, (size_t)esrk::glob_blocks(mp) * esrk::kGlobParts *
                                      sizeof(double)) == hipSuccess &&
-       hipMalloc(&x->glob_out, esrk::kGlobParts * sizeof(double)) == hipSuccess;
+       hipMalloc(&x->glob_state, sizeof(esrk::GlobState)) == hipSuccess;
   if (x->nslots > 0)
     ok = ok && hipMalloc(&x->kst, (size_t)x->nslots * len * sizeof(double)) == hipSuccess;
   if (x->order_emb > 0)
@@ -486,7 +365,7 @@ void esrk_destroy(esrk_ctx* x) {
   (void)hipFree(x->vdiss);
   (void)hipFree(x->relax_parts);
   (void)hipFree(x->glob_parts);
-  (void)hipFree(x->glob_out);
+  (void)hipFree(x->glob_state);
   (void)hipFree(x->kst);
   (void)hipFree(x->err);
   (void)hipFree(x->errk);
@@ -675,14 +554,13 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
     r.check_reject = adaptive ? 1 : 0;
     r.phi0_in = x->phi0acc;
     e = esrk::launch_relax(x->mp, r, s);
+  } else if (x->relax_mode == ESRK_RELAX_GLOBAL) {
+    e = esrk::launch_glob_solve(x->mp, u, x->du, x->deta, x->phi0acc, x->glob_state,
+                                x->glob_parts, x->relax_parts, x->scal, 1, adaptive ? 1 : 0,
+                                x->cfg.root_tol, x->cfg.gamma_max, kGlobMaxPasses, s);
+    nparts = 1;
   } else {
-    double g = INFINITY;  // +inf partial: the update takes gamma = 1
-    if (x->relax_mode == ESRK_RELAX_GLOBAL) {
-      const esrk_status st =
-          global_solve(x, u, x->du, x->deta, x->phi0acc, &g, nullptr, true, adaptive, s);
-      if (st != ESRK_OK) return st;
-    }
-    e = esrk::launch_set_part(x->relax_parts, g, s);
+    e = esrk::launch_set_part(x->relax_parts, INFINITY, s);  // the update takes gamma = 1
     nparts = 1;
   }
   if (e == hipSuccess)
@@ -758,13 +636,17 @@ esrk_status esrk_global_relaxation_solve(esrk_ctx* x, const double* u_old, const
   if (!x || !u_old || !du || !deta || !gamma) return ESRK_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   x->last = s;
-  double g = 1.0;
-  const esrk_status st = global_solve(x, u_old, du, deta, nullptr, &g, passes, false, false, s);
-  if (st != ESRK_OK) return st;
-  if (hipMemcpyAsync(gamma, &g, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return ESRK_EHIP;
-  return ESRK_OK;
+  esrk::GlobState h;
+  hipError_t e = esrk::launch_glob_solve(x->mp, u_old, du, deta, nullptr, x->glob_state,
+                                         x->glob_parts, x->relax_parts, x->scal, 0, 0,
+                                         x->cfg.root_tol, x->cfg.gamma_max, kGlobMaxPasses, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(gamma, &x->glob_state->gamma, sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, x->glob_state, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return ESRK_EHIP;
+  if (passes) *passes = h.passes;
+  return (esrk_status)h.status;
 }
 
 esrk_status esrk_local_relaxation_solve_ml(esrk_ctx* x, const double* u_old, const double* du,

@@ -200,11 +200,27 @@ struct GlobTrials {
   double g[kGlobTrials];
 };
 int glob_blocks(const MeshParams& mp);
-// phi0_in (nullable): per-element phi_k(0), summed in place of A - sum deta
-hipError_t launch_glob_eval(const MeshParams& mp, const double* u_old, const double* du,
-                            const double* deta, const double* phi0_in, int first,
-                            const GlobTrials& trials, double* parts, double* out,
-                            hipStream_t s);
+// Device state of the global relaxation solve (bracket, trial values, result).
+struct GlobState {
+  double lo, flo, hi, fhi, s_prev, gamma, phi0, noise;
+  double g[kGlobTrials];
+  int stage;   // 0 first pass, 1 expanding the bracket, 2 refining, 3 done
+  int halved;  // the last refining pass halved the bracket
+  int passes;  // device passes that did work
+  int status;  // ESRK_OK, ESRK_ENOROOT or ESRK_ENAN
+};
+// Global relaxation on the device: max_passes sweeps of four trial values
+// (a sweep after convergence returns at once), the bracket logic in a
+// one-block kernel between sweeps, no host synchronization.  phi0_in
+// (nullable): per-element phi_k(0), summed in place of A - sum deta.  The
+// result goes to st->gamma and to rparts[0] for the update; with latch, an
+// error is latched in scal like the local solve's; with check_reject, a
+// rejected error-controlled attempt is skipped.
+hipError_t launch_glob_solve(const MeshParams& mp, const double* u_old, const double* du,
+                             const double* deta, const double* phi0_in, GlobState* st,
+                             double* parts, RelaxPart* rparts, DevScalars* scal, int latch,
+                             int check_reject, double tol, double gmax, int max_passes,
+                             hipStream_t s);
 hipError_t launch_set_part(RelaxPart* parts, double g, hipStream_t s);
 hipError_t launch_relax(const MeshParams& mp, const RelaxArgs& a, hipStream_t s);
 // gamma = min over partials (1 if all inactive) -> *gamma and scal->gamma

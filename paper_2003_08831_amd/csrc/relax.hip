@@ -833,8 +833,13 @@ hipError_t launch_adapt(const double* errk, int ne, double count, int q, int dec
 template <int DIM, int N>
 __global__ void __launch_bounds__(256) glob_eval_kernel(const MeshParams mp, const double* u_old,
                                                         const double* du, const double* deta,
-                                                        const double* phi0_in, int first,
-                                                        GlobTrials trials, double* parts) {
+                                                        const double* phi0_in,
+                                                        const GlobState* st, double* parts) {
+  if (st->stage == 3) return;  // converged: the remaining sweeps do nothing
+  const int first = st->stage == 0;
+  GlobTrials trials;
+#pragma unroll
+  for (int j = 0; j < kGlobTrials; ++j) trials.g[j] = st->g[j];
   constexpr int ND = (DIM == 1) ? N : (DIM == 2) ? N * N : N * N * N;
   constexpr int NV = DIM + 2;
   const MeshDims md = dims_of(mp);
@@ -963,22 +968,177 @@ __global__ void __launch_bounds__(256) glob_eval_kernel(const MeshParams mp, con
   }
 }
 
-// Sum of the block partials (fixed order) -> out[kGlobParts].
-__global__ void __launch_bounds__(256) glob_reduce_kernel(const double* parts, int nparts,
-                                                          double* out) {
+// Trial points of the next refining sweep: four points around the regula
+// falsi estimate c (+-w/2, +-3w/2, w twice the last correction), or four
+// evenly spaced points when the last sweep did not halve the bracket.
+__device__ void glob_choose(GlobState& S, double tol) {
+  const double width = S.hi - S.lo;
+  const double tw = tol * fmax(1.0, S.hi);
+  if (S.halved) {
+    double c = isinf(S.fhi) ? 0.5 * (S.lo + S.hi) : S.lo - S.flo * width / (S.fhi - S.flo);
+    if (!(c == c)) c = 0.5 * (S.lo + S.hi);
+    c = fmin(fmax(c, S.lo + 0.25 * tw), S.hi - 0.25 * tw);
+    double w = (S.s_prev == S.s_prev) ? 2.0 * fabs(c - S.s_prev) : 1e-3 * width;
+    w = fmax(w, 0.25 * tw);
+    for (int j = 0; j < kGlobTrials; ++j) {
+      const double g = c + (j - 0.5 * (kGlobTrials - 1)) * w;
+      S.g[j] = fmin(fmax(g, S.lo + 0.125 * tw), S.hi - 0.125 * tw);
+    }
+    S.s_prev = c;
+  } else {
+    for (int j = 0; j < kGlobTrials; ++j) S.g[j] = S.lo + (j + 1) * width / (kGlobTrials + 1);
+  }
+}
+
+__device__ void glob_expand(GlobState& S, double gmax) {
+  for (int j = 0; j < kGlobTrials; ++j) S.g[j] = fmin(S.lo * (double)(2 << j), gmax);
+}
+
+// Sum of the block partials (fixed order), then one step of the bracket logic
+// (thread 0): inactive (gamma = 1) when B(1) is at the round-off level,
+// ESRK_ENOROOT when phi(0) >= 0, bracket [0, 1] doubled up to gmax, then
+// refining sweeps until the bracket is narrower than tol max(1, gamma); the
+// lower end is the result.
+__global__ void __launch_bounds__(256) glob_logic_kernel(const double* parts, int nparts,
+                                                         GlobState* st, RelaxPart* rparts,
+                                                         DevScalars* scal, int latch,
+                                                         int check_reject, double tol,
+                                                         double gmax, int max_passes) {
+  if (st->stage == 3) return;
   __shared__ double red[256];
+  __shared__ double o[kGlobParts];
   for (int q = 0; q < kGlobParts; ++q) {
     double s = 0.0;
     for (int b = threadIdx.x; b < nparts; b += 256) s += parts[(long long)b * kGlobParts + q];
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[q] = red[0];
+    if (threadIdx.x == 0) o[q] = red[0];
     __syncthreads();
   }
+  if (threadIdx.x != 0) return;
+  GlobState S = *st;
+  S.passes += 1;
+  auto phi_at = [&](double g, double Bg) { return isfinite(Bg) ? S.phi0 + Bg / g : INFINITY; };
+  bool done = false;
+  double result = INFINITY;
+  if (S.stage == 0) {
+    if ((check_reject && scal->rejected) || (latch && scal->status != 0)) {
+      done = true;  // nothing to relax: a rejected attempt, or an error already latched
+    } else if (!isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[3])) {
+      S.status = ESRK_ENAN;
+      if (latch) latch_r(scal, ESRK_ENAN, 0x7fffffffffffffffLL);
+      done = true;
+    } else {
+      S.phi0 = o[0] - o[2];
+      S.noise = 64.0 * DBL_EPSILON * (o[1] + o[3]);
+      const double B1 = o[4];
+      if (isfinite(B1) && B1 <= S.noise) {
+        result = 1.0;
+        done = true;
+      } else if (!(S.phi0 < 0.0)) {
+        S.status = ESRK_ENOROOT;
+        if (latch) latch_r(scal, ESRK_ENOROOT, 0x7fffffffffffffffLL);
+        done = true;
+      } else {
+        S.lo = 0.0;
+        S.flo = S.phi0;
+        S.hi = 1.0;
+        S.fhi = phi_at(1.0, B1);
+        S.s_prev = NAN;
+        S.halved = 1;
+        if (!(S.fhi > 0.0)) {
+          S.lo = 1.0;
+          S.flo = S.fhi;
+          S.stage = 1;
+          glob_expand(S, gmax);
+        } else {
+          S.stage = 2;
+          glob_choose(S, tol);
+        }
+      }
+    }
+  } else if (S.stage == 1) {
+    bool found = false;
+    for (int j = 0; j < kGlobTrials; ++j) {
+      if (found) continue;
+      const double f = phi_at(S.g[j], o[4 + j]);
+      if (f > 0.0) {
+        S.hi = S.g[j];
+        S.fhi = f;
+        found = true;
+      } else {
+        S.lo = S.g[j];
+        S.flo = f;
+      }
+    }
+    if (found) {
+      S.stage = 2;
+      S.halved = 1;
+      S.s_prev = NAN;
+      if (S.hi - S.lo <= tol * fmax(1.0, S.hi)) {
+        result = S.lo;
+        done = true;
+      } else {
+        glob_choose(S, tol);
+      }
+    } else if (S.lo >= gmax) {
+      result = gmax;
+      done = true;
+    } else {
+      glob_expand(S, gmax);
+    }
+  } else {
+    const double width = S.hi - S.lo;
+    for (int j = 0; j < kGlobTrials; ++j) {
+      const double f = phi_at(S.g[j], o[4 + j]);
+      if (f <= 0.0) {
+        if (S.g[j] > S.lo) {
+          S.lo = S.g[j];
+          S.flo = f;
+        }
+      } else if (S.g[j] < S.hi) {
+        S.hi = S.g[j];
+        S.fhi = f;
+      }
+    }
+    S.halved = (S.hi - S.lo) <= 0.5 * width;
+    if (S.hi - S.lo <= tol * fmax(1.0, S.hi)) {
+      result = S.lo;
+      done = true;
+    } else {
+      glob_choose(S, tol);
+    }
+  }
+  if (!done && S.passes >= max_passes) {
+    result = S.lo;  // phi(lo) <= 0: the relaxed total entropy does not exceed the estimate
+    done = true;
+  }
+  if (done) {
+    S.gamma = result;
+    S.stage = 3;
+    rparts[0] = RelaxPart{result, 0, 0, 0};
+  }
+  *st = S;
+}
+
+// Starts a global solve: first sweep at gamma = 1.
+__global__ void glob_init_kernel(GlobState* st, RelaxPart* rparts) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  GlobState S;
+  S.lo = S.flo = S.hi = S.fhi = S.phi0 = S.noise = 0.0;
+  S.s_prev = NAN;
+  S.gamma = INFINITY;
+  for (int j = 0; j < kGlobTrials; ++j) S.g[j] = 1.0;
+  S.stage = 0;
+  S.halved = 1;
+  S.passes = 0;
+  S.status = ESRK_OK;
+  *st = S;
+  rparts[0] = RelaxPart{INFINITY, 0, 0, 0};
 }
 
 // One relaxation partial carrying a given gamma (+inf: relaxation off), for
@@ -989,14 +1149,18 @@ __global__ void set_part_kernel(RelaxPart* parts, double g) {
 
 int glob_blocks(const MeshParams& mp) { return (mp.ne * mp.nd + 255) / 256; }
 
-hipError_t launch_glob_eval(const MeshParams& mp, const double* u_old, const double* du,
-                            const double* deta, const double* phi0_in, int first,
-                            const GlobTrials& trials, double* parts, double* out,
-                            hipStream_t s) {
+hipError_t launch_glob_solve(const MeshParams& mp, const double* u_old, const double* du,
+                             const double* deta, const double* phi0_in, GlobState* st,
+                             double* parts, RelaxPart* rparts, DevScalars* scal, int latch,
+                             int check_reject, double tol, double gmax, int max_passes,
+                             hipStream_t s) {
   const int blocks = glob_blocks(mp);
+  hipLaunchKernelGGL(glob_init_kernel, dim3(1), dim3(64), 0, s, st, rparts);
+  hipError_t e = hipGetLastError();
+  for (int pass = 0; pass < max_passes && e == hipSuccess; ++pass) {
 #define ESRK_GE(D, NN)                                                                  \
   hipLaunchKernelGGL((glob_eval_kernel<D, NN>), dim3(blocks), dim3(256), 0, s, mp, u_old, \
-                     du, deta, phi0_in, first, trials, parts)
+                     du, deta, phi0_in, st, parts)
 #define ESRK_GD(D)                     \
   switch (mp.n) {                      \
     case 2: ESRK_GE(D, 2); break;      \
@@ -1006,13 +1170,16 @@ hipError_t launch_glob_eval(const MeshParams& mp, const double* u_old, const dou
     case 6: ESRK_GE(D, 6); break;      \
     default: return hipErrorInvalidValue; \
   }
-  if (mp.dim == 1) { ESRK_GD(1) } else if (mp.dim == 2) { ESRK_GD(2) } else { ESRK_GD(3) }
+    if (mp.dim == 1) { ESRK_GD(1) } else if (mp.dim == 2) { ESRK_GD(2) } else { ESRK_GD(3) }
 #undef ESRK_GD
 #undef ESRK_GE
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(glob_reduce_kernel, dim3(1), dim3(256), 0, s, parts, blocks, out);
-  return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(glob_logic_kernel, dim3(1), dim3(256), 0, s, parts, blocks, st, rparts,
+                       scal, latch, check_reject, tol, gmax, max_passes);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_set_part(RelaxPart* parts, double g, hipStream_t s) {
