@@ -78,7 +78,7 @@ typedef struct {
   double prandtl;      /* Prandtl number */
   double lambda_scale; /* interface dissipation: 1 = local Lax-Friedrichs, 0 = EC surface */
   int precision;       /* ESRK_FP64, or ESRK_FP32_FLUX (flux differencing in FP32) */
-  int tableau;         /* ESRK_SSPRK33 or ESRK_RK44 (both have b_i >= 0) */
+  int tableau;         /* ESRK_SSPRK33, ESRK_RK44, ESRK_BSRK43 or ESRK_BSRK85 (all b_i >= 0) */
   double cfl;          /* dt = cfl * min h / ((deg+1) * max_i sum_m (|v_m| + c)) */
   double root_tol;     /* relaxation bracket width, relative to max(1, gamma) */
   int root_maxit;      /* iteration cap of the per-element root solve */
