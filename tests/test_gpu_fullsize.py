@@ -5,8 +5,10 @@ Taylor-Green runs, SSPRK(3,3) for the vortex and the Kelvin-Helmholtz batch).
 * 2-D isentropic vortex 8x8 p=3: all 100 steps, each started from the
   oracle's state.
 * 3-D Euler Taylor-Green 16^3 p=3: the whole right-hand side against the
-  oracle (FP64 and FP32 flux), two relaxed steps, and 50 free-running steps
-  checked for conservation and total-entropy decay.
+  oracle (FP64 and FP32 flux), two relaxed steps, the global relaxation root
+  and the local roots from the stage-wise phi_k(0), two error-controlled
+  BSRK(4,3) attempts, and 50 free-running steps checked for conservation and
+  total-entropy decay.
 * 3-D Navier-Stokes Taylor-Green 32^3 p=4: the whole right-hand side and the
   element viscous dissipation against the oracle (FP64), and FP32 (MFMA
   divergence) conservation.
@@ -128,6 +130,81 @@ def test_tgv16_p3_two_steps(tgv16):
     t = 0.0
     for step in range(2):
         u, t = _check_step(ctx, ms, m, O.RK44, u, t, 0.5, stats, step)
+    assert ctx.sync_status()[0] == 0
+
+
+def test_tgv16_p3_global_relaxation_and_stagewise_roots(tgv16):
+    """Full size, RK(4,4) increments from the device's own stages: the global
+    relaxation root against the oracle's on the same increments, and the
+    local roots from the stage-wise phi_k(0) against the oracle's from its
+    own stages (the bound of the stage-wise test at small size)."""
+    from tests.test_gpu_global import glob_tolerance
+    ms, m, u, _, _ = tgv16
+    ctx = ctx_for(ms, tableau=esrk.RK44, cfl=0.5)
+    dt = O.cfl_dt(m, u, 0.5)
+    ud = dev(u)
+    bufs = [zeros(u.size), zeros(u.size)]
+    du, deta, phi0 = zeros(u.size), zeros(ctx.ne), zeros(ctx.ne)
+    yin = ud
+    for i in range(4):
+        yout = bufs[i % 2] if i < 3 else None
+        ctx.rk_stage(i, dt, ud, yin, yout, du, deta)
+        yin = yout
+    ctx.stage_phi0(phi0)
+    duh, detah = host(du), host(deta)
+    ref = O.global_relaxation_solve(m, u, duh, detah)
+    assert ref["rc"] == 0
+    gam = zeros(1)
+    passes = ctx.global_relaxation_solve(ud, du, deta, gam)
+    assert abs(host(gam)[0] - ref["gamma"]) <= glob_tolerance(ref), (host(gam)[0], ref)
+    # local roots with phi_k(0) from the stages, on the device's increments,
+    # against the oracle's solve on the same increments and phi_k(0)
+    gk, gl = zeros(ctx.ne), zeros(1)
+    ctx.local_relaxation_solve_phi0(ud, du, deta, phi0, gk, gl)
+    loc = O.local_relaxation_solve(m, u, duh, detah, a=host(phi0))
+    assert loc["rc"] == 0
+    g, g_ref = host(gk), loc["gamma_k"]
+    fin = np.isfinite(g_ref) & np.isfinite(g)
+    tol = 2e-12 * np.maximum(1.0, g_ref[fin]) + 1e-3 * loc["noise"][fin] / loc["curv"][fin]
+    assert np.all(np.abs(g[fin] - g_ref[fin]) <= tol)
+    print(f"\n[TGV 16^3 p3] global gamma {host(gam)[0]!r} (oracle {ref['gamma']!r}, {passes} passes); "
+          f"local max |dgamma_k| {np.abs(g[fin] - g_ref[fin]).max():.2e} over {fin.sum()} elements")
+    assert ctx.sync_status()[0] == 0
+
+
+def test_tgv16_p3_error_controlled_attempt(tgv16):
+    """Full size, BSRK(4,3) with tolerance 1e-6: two error-controlled attempts
+    with the device's step sizes, each repeated by the oracle from the same
+    state with that step: error norm, decision, gamma and state."""
+    ms, m, u, _, _ = tgv16
+    ctx = ctx_for(ms, tableau=esrk.BSRK43, cfl=0.5)
+    ctx.set_adaptive(1e-6, 1e-6)
+    ud, t, st = dev(u), zeros(1), zeros(8)
+    t_ref = 0.0
+    for attempt in range(2):
+        u_before = u.copy()
+        ctx.step(ud, t, 0.0, None, st)
+        s = host(st)
+        r = O.adaptive_step(m, O.BSRK43, u, t_ref, dt=s[1], mode=O.RELAX_LOCAL, atol=1e-6,
+                            rtol=1e-6, cfl=0.5)
+        assert r["rc"] == 0
+        assert abs(s[6] - r["err"]) <= 1e-6 * r["err"], (s[6], r["err"])
+        assert bool(s[7]) == r["accepted"]
+        du, deta, a = O.rk_step_a(m, O.BSRK43, u_before, s[1])
+        loc = O.local_relaxation_solve(m, u_before, du, deta, a=a)
+        fin = np.isfinite(loc["gamma_k"])
+        k = np.argmin(np.where(fin, loc["gamma_k"], np.inf))
+        gtol = 2e-12 + 1e-3 * loc["noise"][k] / loc["curv"][k] + 1e-10
+        if r["accepted"]:
+            assert abs(s[0] - r["gamma"]) <= gtol, (s[0], r["gamma"])
+        got = host(ud).reshape(ms.nv, -1)
+        ref = u.reshape(ms.nv, -1)
+        for v in range(ms.nv):
+            tolv = RTOL * np.abs(ref[v]).max() + gtol * np.abs(du.reshape(ms.nv, -1)[v]).max()
+            assert np.abs(got[v] - ref[v]).max() <= tolv, (attempt, v)
+        t_ref = r["t"]
+        ud.copy_(dev(u))
+        t.fill_(t_ref)
     assert ctx.sync_status()[0] == 0
 
 
