@@ -379,6 +379,8 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
   // segment; otherwise they go through LDS.
   constexpr int ITER = (EN + TH - 1) / TH;
   constexpr bool kWaveRed = (ND & (ND - 1)) == 0 && ND <= 64 && TH % 64 == 0;
+  // one element per block otherwise (3-D, p >= 4): block-wide sums
+  constexpr bool kBlockRed = !kWaveRed && E == 1 && TH % 64 == 0;
   double wdv[ITER], esq[ITER], psi[ITER];
 #pragma unroll
   for (int it = 0; it < ITER; ++it) wdv[it] = esq[it] = psi[it] = 0.0;
@@ -389,7 +391,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
     const int e = idx / ND;
     const int k = k0 + e;
     if (k >= md.ne) {
-      if (!kWaveRed) sred[idx] = 0.0;
+      if (!kWaveRed && !kBlockRed) sred[idx] = 0.0;
       continue;
     }
     const int i = idx - e * ND;
@@ -447,7 +449,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       }
     }
     wdv[it] = M * wdot;
-    if (!kWaveRed) sred[idx] = wdv[it];
+    if (!kWaveRed && !kBlockRed) sred[idx] = wdv[it];
 
     if (a.stage_mode) {
       const double cdt = a.sc.c * dt, bdt = a.sc.b * dt;
@@ -527,6 +529,50 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
         if (a.stage_mode && a.phi0) a.phi0[k] = (a.first ? 0.0 : a.phi0[k]) + a.sc.b * dt * sp;
         if (errk) errk[k] = se;
       }
+    }
+    return;
+  }
+  if constexpr (kBlockRed) {
+    // per thread in a fixed order, then butterfly shuffles within each wave,
+    // then the waves' partials in LDS summed by thread 0 in wave order
+    double s = 0.0, sp = 0.0, se = 0.0;
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      s += wdv[it];
+      sp += psi[it];
+      se += esq[it];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off /= 2) {
+      s += __shfl_xor(s, off, 64);
+      sp += __shfl_xor(sp, off, 64);
+      se += __shfl_xor(se, off, 64);
+    }
+    constexpr int NW = TH / 64;
+    static_assert(3 * NW <= EN, "wave partials fit the reduction buffer");
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0) {
+      sred[3 * wave] = s;
+      sred[3 * wave + 1] = sp;
+      sred[3 * wave + 2] = se;
+    }
+    __syncthreads();
+    if (tid == 0 && k0 < md.ne) {
+      double ts = 0.0, tp = 0.0, te = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        ts += sred[3 * w];
+        tp += sred[3 * w + 1];
+        te += sred[3 * w + 2];
+      }
+      const int k = k0;
+      if (a.eta) {
+        if (a.stage_mode)
+          a.eta[k] = (a.first ? 0.0 : a.eta[k]) + a.sc.b * dt * ts;
+        else
+          a.eta[k] = ts;
+      }
+      if (a.stage_mode && a.phi0) a.phi0[k] = (a.first ? 0.0 : a.phi0[k]) + a.sc.b * dt * tp;
+      if (errk) errk[k] = te;
     }
     return;
   }
