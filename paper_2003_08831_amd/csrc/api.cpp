@@ -521,7 +521,9 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
     a.u_old = u;
     a.out = last ? nullptr : bufs[i & 1];
     a.du = x->du;
-    a.eta = x->deta;
+    // the solves take phi_k(0) from the stages, so the estimate's increment
+    // itself is needed only for the network's features
+    a.eta = x->step_model ? x->deta : nullptr;
     if (i == 0) {
       a.speed_parts = cfl ? x->speed_parts : nullptr;
       a.dt_dev = proposal ? &x->scal->dt_next : nullptr;
@@ -546,7 +548,8 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
   int nparts = x->n_relax_parts;
   if (x->relax_mode == ESRK_RELAX_LOCAL) {
     double* gk = gamma_k_out ? gamma_k_out : x->gamma_k;
-    esrk::RelaxArgs r = relax_args(x, u, x->du, x->deta, nullptr, gk, x->iters);
+    esrk::RelaxArgs r =
+        relax_args(x, u, x->du, x->step_model ? x->deta : nullptr, nullptr, gk, x->iters);
     r.model = x->step_model;
     r.feats = x->step_feats;
     r.dt_dev = &x->scal->dt;
@@ -555,7 +558,7 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
     r.phi0_in = x->phi0acc;
     e = esrk::launch_relax(x->mp, r, s);
   } else if (x->relax_mode == ESRK_RELAX_GLOBAL) {
-    e = esrk::launch_glob_solve(x->mp, u, x->du, x->deta, x->phi0acc, x->glob_state,
+    e = esrk::launch_glob_solve(x->mp, u, x->du, nullptr, x->phi0acc, x->glob_state,
                                 x->glob_parts, x->relax_parts, x->scal, 1, adaptive ? 1 : 0,
                                 x->cfg.root_tol, x->cfg.gamma_max, kGlobMaxPasses, s);
     nparts = 1;

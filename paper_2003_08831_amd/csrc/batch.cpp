@@ -105,7 +105,7 @@ hipError_t enqueue_step(esrk_batch* b, double* u, double* t, double* gamma, int 
     a.u_old = u;
     a.out = last ? nullptr : bufs[i & 1];
     a.du = b->du;
-    a.eta = b->deta;
+    a.eta = nullptr;  // the solve takes phi_k(0) from the stages
     a.phi0 = b->phi0acc;
     a.speed_parts = i == 0 ? b->speed_parts : nullptr;
     a.sc = b->sc[i];
@@ -122,7 +122,7 @@ hipError_t enqueue_step(esrk_batch* b, double* u, double* t, double* gamma, int 
     esrk::RelaxArgs r{};
     r.u_old = u;
     r.du = b->du;
-    r.deta = b->deta;
+    r.deta = nullptr;
     r.phi0_in = b->phi0acc;
     r.guess = nullptr;
     r.gamma_k = b->gamma_k;
@@ -336,7 +336,7 @@ esrk_status esrk_batch_autotune(esrk_batch* b, const double* u, int reps, int* t
   a.u_old = u;
   a.out = b->ya;
   a.du = b->du;
-  a.eta = b->deta;
+  a.phi0 = b->phi0acc;  // as in the steps: phi_k(0), no entropy rate
   a.sc = b->sc[1];
   a.stage_mode = 1;
   a.first = 1;

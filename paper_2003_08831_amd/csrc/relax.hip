@@ -256,8 +256,10 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
   A = seg_sum<G>(A);
   scale = seg_sum<G>(scale);
   if (want_feats) smax = seg_max<G>(smax);
-  const double deta = valid ? a.deta[k] : 0.0;
-  const double phi0 = a.phi0_in ? (valid ? a.phi0_in[k] : 0.0) : A - deta;
+  // phi_k(0) from the stages when given; the estimate's increment is then
+  // Delta eta_k = A_k - phi_k(0) if the caller did not pass it
+  const double phi0 = a.phi0_in ? (valid ? a.phi0_in[k] : 0.0) : A - (valid ? a.deta[k] : 0.0);
+  const double deta = (valid && a.deta) ? a.deta[k] : A - phi0;
   // round-off level of the element's entropy increments: FP64 increments, or
   // increments built from FP32 flux differences (then the estimate and the
   // update of an element that barely changes are FP32 noise and its root is
@@ -565,7 +567,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     RelaxArgs a = a0;
     a.u_old = a0.u_old + P.base;
     a.du = a0.du + P.base;
-    a.deta = a0.deta + P.elem_base;
+    a.deta = a0.deta ? a0.deta + P.elem_base : nullptr;
     a.phi0_in = a0.phi0_in ? a0.phi0_in + P.elem_base : nullptr;
     a.guess = a0.guess ? a0.guess + P.elem_base : nullptr;
     a.gamma_k = a0.gamma_k + P.elem_base;
@@ -904,10 +906,17 @@ __global__ void __launch_bounds__(256) glob_eval_kernel(const MeshParams mp, con
       } else {
         acc[0] = M * t;
       }
-      if (i == 0) {
-        const double de = deta[gi / ND];
-        acc[2] = phi0_in ? 0.0 : de;
-        acc[3] = fabs(de);
+      if (deta) {
+        if (i == 0) {
+          const double de = deta[gi / ND];
+          acc[2] = phi0_in ? 0.0 : de;
+          acc[3] = fabs(de);
+        }
+      } else {
+        // no estimate passed (phi0_in given): |Delta eta_k| = |A_k - phi_k(0)|
+        // is at most the element's scale plus |phi_k(0)|
+        acc[1] *= 2.0;
+        if (i == 0) acc[3] = fabs(phi0_in[gi / ND]);
       }
     }
 #pragma unroll

@@ -414,25 +414,22 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       kv[v] = -double(s);
       if (a.visc) kv[v] += a.visc[v * Ntot + gi];
     }
-    // entropy variables in FP64: w = [(g - s)/(g-1) - beta |v|^2, 2 beta v, -2 beta]
-    // (primitives recomputed from y: their LDS slots now hold the accumulators)
-    double rho, beta, v2, vel[DIM];
-    {
+    // entropy rate w(y).k in FP64, w = [(g - s)/(g-1) - beta |v|^2, 2 beta v,
+    // -2 beta] (primitives recomputed from y: their LDS slots now hold the
+    // accumulators); not formed when nobody reads it (a step that solves
+    // with phi_k(0) from the stages)
+    double wdot = 0.0;
+    if (a.eta) {
       Prim<double, DIM> P;
       double p;
       prim_from_cons<double, DIM>(yv, ggd, P, p);
-      rho = P.rho;
-      beta = P.beta;
-      v2 = P.v2;
+      const double lnr = log_d(P.rho), lnb = log_d(P.beta);
+      const double s_phys = (1.0 - ggd) * lnr - 0.6931471805599453 - lnb;  // ln p - g ln rho
+      wdot = ((ggd - s_phys) * inv_gm1d - P.beta * P.v2) * kv[0];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) vel[d] = P.v[d];
+      for (int d = 0; d < DIM; ++d) wdot += 2.0 * P.beta * P.v[d] * kv[1 + d];
+      wdot += -2.0 * P.beta * kv[NV - 1];
     }
-    const double lnr = log_d(rho), lnb = log_d(beta);
-    const double s_phys = (1.0 - ggd) * lnr - 0.6931471805599453 - lnb;  // ln p - g ln rho
-    double wdot = ((ggd - s_phys) * inv_gm1d - beta * v2) * kv[0];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) wdot += 2.0 * beta * vel[d] * kv[1 + d];
-    wdot += -2.0 * beta * kv[NV - 1];
     double M = 1.0;
     {
       int ii = i;
