@@ -39,6 +39,13 @@ FLOP_PAIR, FLOP_FACE, FLOP_NODE = 90.0, 130.0, 80.0
 # read y, u_old, du; write du, y_next.
 BYTES_NODE_STAGE = 5 * 5 * 8
 
+# Measured HBM traffic of that launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+# calibrated on a copy kernel) and the hash of the stage-kernel sources it was
+# taken on; the figure is reported only while those sources are unchanged.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "rhs_kernel_tgv16_p3_traffic.md")
+STAGE_SOURCES = ("paper_2003_08831_amd/csrc/rhs.hip", "paper_2003_08831_amd/csrc/device_math.h",
+                 "paper_2003_08831_amd/csrc/internal.h")
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -49,7 +56,7 @@ def parse():
     p.add_argument("--cpu-steps", type=int, default=3)
     p.add_argument("--kernel-reps", type=int, default=50)
     p.add_argument("--copy-calib", action="store_true",
-                   help="run one 256 MiB device-to-device copy first (counter calibration)")
+                   help="run one 256 MiB device copy kernel first (counter calibration)")
     p.add_argument("--no-variants", action="store_true",
                    help="skip the Navier-Stokes, batched and learned-guess measurements")
     return p.parse_args()
@@ -263,12 +270,13 @@ def root_methods_variant(esrk, I, torch, steps=10, warmup=2):
 
 
 def time_stage_kernel(esrk, torch, ctx, u, reps):
-    """Average duration of one fused stage-kernel launch (middle RK stage),
-    HIP events on the launch stream (the default stream)."""
+    """Average duration of one fused stage-kernel launch (middle RK stage, in
+    the configuration esrk_step launches it: phi_k(0) accumulated, no separate
+    entropy rate), HIP events on the launch stream (the default stream)."""
     n = u.numel()
     ya = torch.empty(n, dtype=torch.float64, device="cuda")
     du = torch.zeros(n, dtype=torch.float64, device="cuda")
-    deta = torch.zeros(ctx.ne, dtype=torch.float64, device="cuda")
+    deta = None
     dt = 1e-3
     ctx.rk_stage(0, dt, u, u, ya, du, deta)
     for _ in range(3):
@@ -281,6 +289,26 @@ def time_stage_kernel(esrk, torch, ctx, u, reps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def measured_traffic():
+    """HBM bytes per stage-kernel launch from the committed counter summary,
+    or None when it is missing or was taken on other kernel sources."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for s in STAGE_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    sha = re.search(r"sha256 over [^`]*`([0-9a-f]{64})`", text)
+    tot = re.search(r"\| total HBM bytes per launch \| (\d+) \|", text)
+    if not sha or not tot or sha.group(1) != h.hexdigest():
+        return None
+    return int(tot.group(1))
 
 
 def cpu_baseline(I, steps):
@@ -315,7 +343,7 @@ def main():
     if a.copy_calib:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)  # one elementwise kernel: reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         del src, dst
 
@@ -336,16 +364,21 @@ def main():
     gbs = N * BYTES_NODE_STAGE / (kms * 1e-3) / 1e9
     alu_frac = tflops / FP64_VECTOR_PEAK_TFLOPS
     hbm_frac = gbs / HBM_PEAK_GBS
+    traffic = measured_traffic()
     if alu_frac >= hbm_frac:
         roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": None}
+                "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": traffic}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": None}
+                "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": traffic}
     roof.update({"kernel": "rhs_kernel<3,4,double> (fused RK stage)",
                  "kernel_ms": round(kms, 4),
+                 "traffic_unit": "HBM bytes per launch",
                  "other": {"hbm_GBs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4),
-                           "fp64_TFLOPs": round(tflops, 3), "alu_frac": round(alu_frac, 4)}})
+                           "fp64_TFLOPs": round(tflops, 3), "alu_frac": round(alu_frac, 4),
+                           "algorithmic_bytes_per_launch": N * BYTES_NODE_STAGE,
+                           "traffic_GBs": (round(traffic / (kms * 1e-3) / 1e9, 1)
+                                           if traffic else None)}})
 
     out = {
         "metric": "DOF-stage updates/s incl. local relaxation, FP32-mixed vs FP64, 1 MI355X",

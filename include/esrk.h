@@ -125,7 +125,10 @@ esrk_status esrk_rhs_ns(esrk_ctx* ctx, const double* u, double* dudt, double* et
  * BSRK(4,3) and BSRK(8,5) form y_out from u_old and the slopes of earlier
  * stages, which the context stores: run the stages of one step in order, with
  * the same u_old and dt.  They also accumulate the embedded pair's error
- * estimate in the context (esrk_error_estimate). */
+ * estimate in the context (esrk_error_estimate).  Every stage also adds its
+ * part of phi_k(0) to the context's accumulator (esrk_stage_phi0); deta may
+ * be NULL, and then the entropy rate w(y_in).k is not formed (what esrk_step
+ * does: its solves need only phi_k(0)). */
 esrk_status esrk_rk_stage(esrk_ctx* ctx, int stage, double dt, const double* u_old,
                           const double* y_in, double* y_out, double* du, double* deta,
                           void* stream);

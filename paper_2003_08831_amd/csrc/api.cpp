@@ -412,8 +412,7 @@ esrk_status esrk_rhs_ns(esrk_ctx* x, const double* u, double* dudt, double* eta_
 esrk_status esrk_rk_stage(esrk_ctx* x, int stage, double dt, const double* u_old,
                           const double* y_in, double* y_out, double* du, double* deta,
                           void* stream) {
-  if (!x || stage < 0 || stage >= x->stages || !u_old || !y_in || !du || !deta ||
-      !(dt > 0.0))
+  if (!x || stage < 0 || stage >= x->stages || !u_old || !y_in || !du || !(dt > 0.0))
     return ESRK_EINVAL;
   const bool last = stage == x->stages - 1;
   if (!last && !y_out) return ESRK_EINVAL;

@@ -106,6 +106,38 @@ def test_rk_stage_chain_parity(tab, name, ms, kind):
     assert np.abs(host(deta) - deta_ref).max() <= 1e-11 * np.abs(deta_ref).max()
 
 
+@pytest.mark.parametrize("name,ms,kind", [CASES[2], CASES[7]], ids=["d2p3_vortex", "d3p3_tgv"])
+def test_rk_stage_without_entropy_rate_is_identical(name, ms, kind):
+    """deta = NULL only drops the entropy-rate output: stage values, du and
+    the phi_k(0) accumulator are bit-identical to the run that forms it."""
+    u = make_state(ms, kind, seed=4)
+    m = orc_mesh(O, ms)
+    dt = 0.5 * O.cfl_dt(m, u, 0.5)
+    ud = dev(u)
+    out = []
+    for with_eta in (True, False):
+        ctx = ctx_for(ms, tableau=esrk.RK44)
+        bufs = [zeros(u.size), zeros(u.size)]
+        du = zeros(u.size)
+        deta = zeros(ctx.ne) if with_eta else None
+        ys = []
+        yin = ud
+        for i in range(4):
+            yout = bufs[i % 2] if i < 3 else None
+            ctx.rk_stage(i, dt, ud, yin, yout, du, deta)
+            if yout is not None:
+                ys.append(host(yout).copy())
+            yin = yout
+        phi0 = zeros(ctx.ne)
+        ctx.stage_phi0(phi0)
+        out.append((ys, host(du), host(phi0)))
+    (ys_a, du_a, p_a), (ys_b, du_b, p_b) = out
+    for a, b in zip(ys_a, ys_b):
+        assert np.array_equal(a, b)
+    assert np.array_equal(du_a, du_b)
+    assert np.array_equal(p_a, p_b)
+
+
 def relax_tolerance(ref, gamma_tol=2e-12):
     g = ref["gamma_k"]
     tol = gamma_tol * np.maximum(1.0, np.where(np.isfinite(g), g, 1.0))
