@@ -243,7 +243,7 @@ def root_methods_variant(esrk, I, torch, steps=10, warmup=2):
                            precision=esrk.FP64, tableau=esrk.RK44, cfl=0.5)
     out = {}
     for name, method in (("illinois", esrk.ROOT_ILLINOIS), ("brent", esrk.ROOT_BRENT),
-                         ("bisection", esrk.ROOT_BISECTION)):
+                         ("alefeld", esrk.ROOT_ALEFELD), ("bisection", esrk.ROOT_BISECTION)):
         ctx = esrk.Context(cfg)
         ctx.set_root_method(method)
         u = torch.as_tensor(I.tgv_state(ms, MACH)).to("cuda")

@@ -62,8 +62,9 @@ enum { ESRK_FP64 = 0, ESRK_FP32_FLUX = 1 };
 enum { ESRK_SSPRK33 = 0, ESRK_RK44 = 1, ESRK_BSRK43 = 2, ESRK_BSRK85 = 3 };
 /* Trial-point rule of the relaxation root solves (esrk_set_root_method): all
  * keep the bracket [lo, hi] with phi(lo) <= 0 < phi(hi) and stop at the same
- * width, so they return the same root to root_tol. */
-enum { ESRK_ROOT_ILLINOIS = 0, ESRK_ROOT_BRENT = 1, ESRK_ROOT_BISECTION = 2 };
+ * width (Alefeld also at an exact zero of phi), so they return the same root
+ * to root_tol. */
+enum { ESRK_ROOT_ILLINOIS = 0, ESRK_ROOT_BRENT = 1, ESRK_ROOT_BISECTION = 2, ESRK_ROOT_ALEFELD = 3 };
 /* Relaxation applied by esrk_step (esrk_set_relaxation_mode). */
 enum { ESRK_RELAX_LOCAL = 0, ESRK_RELAX_GLOBAL = 1, ESRK_RELAX_NONE = 2 };
 
@@ -259,9 +260,14 @@ esrk_status esrk_set_dirichlet(esrk_ctx* ctx, const double* u_left, const double
  * the first method of Alefeld, Potra and Shi as robust, secant and Newton as
  * slightly faster): ESRK_ROOT_ILLINOIS (default: regula falsi with the
  * Illinois modification), ESRK_ROOT_BRENT (Brent's inverse quadratic
- * interpolation / secant / bisection safeguards; not with a network's first
- * trial point, which keeps the Illinois rule) or ESRK_ROOT_BISECTION.
- * EINVAL for another value. */
+ * interpolation / secant / bisection safeguards), ESRK_ROOT_ALEFELD (the
+ * first method of Alefeld, Potra and Shi's enclosing algorithm: per iteration
+ * an inverse cubic or Newton-quadratic point, a double-length secant point
+ * and, when the bracket has not halved, its midpoint) or ESRK_ROOT_BISECTION.
+ * Brent and Alefeld do not run with a network's first trial point, which
+ * keeps the Illinois rule.  Every rule stops when the bracket is narrower
+ * than tol max(1, gamma) and returns its lower end.  EINVAL for another
+ * value. */
 esrk_status esrk_set_root_method(esrk_ctx* ctx, int method);
 
 /* Synchronizes `ctx`'s work on the stream of its last call, returns and clears

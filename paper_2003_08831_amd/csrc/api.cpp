@@ -619,7 +619,7 @@ esrk_status esrk_set_dirichlet(esrk_ctx* x, const double* u_left, const double* 
 
 esrk_status esrk_set_root_method(esrk_ctx* x, int method) {
   if (!x || (method != ESRK_ROOT_ILLINOIS && method != ESRK_ROOT_BRENT &&
-             method != ESRK_ROOT_BISECTION))
+             method != ESRK_ROOT_BISECTION && method != ESRK_ROOT_ALEFELD))
     return ESRK_EINVAL;
   x->root_method = method;
   return ESRK_OK;

@@ -157,7 +157,11 @@ struct RelaxCfg {
 
 // One block's work: EPB elements starting at element kb of the mesh md; the
 // block partial goes to a.parts[part].
-template <int DIM, int N, bool NET, bool BRENT = false>
+// Trial-point rules compiled into their own kernels (their per-element state
+// costs registers); kRuleRuntime reads a.method (Illinois or bisection).
+enum { kRuleRuntime = 0, kRuleBrent = 1, kRuleAlefeld = 2 };
+
+template <int DIM, int N, bool NET, int RULE = kRuleRuntime>
 __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims& md,
                                             const RelaxArgs& a, const int kb, const int part,
                                             const long long elem_base) {
@@ -330,9 +334,17 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
   // Brent's method (own instantiation: its state costs registers): previous
   // iterate (ba, fba), last and second-to-last steps
   double ba = NAN, fba = NAN, bd = 0.0, be = 0.0;
-  const int method = BRENT ? ESRK_ROOT_BRENT
-                           : (a.method == ESRK_ROOT_BISECTION ? ESRK_ROOT_BISECTION
-                                                             : ESRK_ROOT_ILLINOIS);
+  // Alefeld-Potra-Shi (first method): phase of the next trial point (0 the
+  // opening secant, 1 inverse cubic / Newton-quadratic, 2 double-length
+  // secant, 3 bisection), the points d and e beside the bracket (e = NaN
+  // until known), d-bar of the current iteration and its opening width
+  int aph = 0;
+  double ad = NAN, fad = NAN, ae = NAN, fae = NAN, adb = NAN, fadb = NAN, aw0 = 0.0;
+  constexpr bool BRENT = RULE == kRuleBrent, ALEFELD = RULE == kRuleAlefeld;
+  const int method = BRENT     ? ESRK_ROOT_BRENT
+                     : ALEFELD ? ESRK_ROOT_ALEFELD
+                               : (a.method == ESRK_ROOT_BISECTION ? ESRK_ROOT_BISECTION
+                                                                  : ESRK_ROOT_ILLINOIS);
   const bool have_guess = a.guess != nullptr;
   double dtf = 0.0;
   if (want_feats) dtf = a.dt_dev ? *a.dt_dev : a.dt_host;
@@ -388,6 +400,14 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
         continue;
       }
     }
+    if (ALEFELD && f == 0.0) {
+      // an exact root ends the enclosure
+      gk = g_trial;
+      done = true;
+      continue;
+    }
+    // the bracket end the new point replaces (d of the enclosure step)
+    const double rep_x = (f <= 0.0) ? lo : hi, rep_f = (f <= 0.0) ? flo : fhi;
     // Illinois: a bracket end kept twice in a row has its value halved
     const bool illinois = method == ESRK_ROOT_ILLINOIS;
     if (f <= 0.0) {
@@ -425,11 +445,104 @@ __device__ __forceinline__ void relax_block(const MeshParams& mp, const MeshDims
       done = true;
       continue;
     }
+    // Alefeld-Potra-Shi bookkeeping for the point just evaluated (a bracketed
+    // point only: the doubling search before the bracket is phase 0)
+    // (phase 0: the point was gamma = 1, a guess or a doubling step, and the
+    // opening secant comes next; phase 4: the opening secant was evaluated)
+    int anext = aph;
+    if (ALEFELD) {
+      if (aph == 4) {
+        // d = the replaced end; the first iteration has no e
+        ad = rep_x;
+        fad = rep_f;
+        anext = 1;
+      } else if (aph == 1) {
+        adb = rep_x;
+        fadb = rep_f;
+        anext = 2;
+      } else if (aph == 2) {
+        if (hi - lo < 0.5 * aw0) {
+          ae = adb;
+          fae = fadb;
+          ad = rep_x;
+          fad = rep_f;
+          anext = 1;
+        } else {
+          ae = rep_x;
+          fae = rep_f;
+          anext = 3;
+        }
+      } else if (aph == 3) {
+        ad = rep_x;
+        fad = rep_f;
+        anext = 1;
+      }
+    }
     double g;
     if (g0 > 0.0) {
       g = g0;
     } else if (method == ESRK_ROOT_BISECTION || isinf(fhi)) {
       g = 0.5 * (lo + hi);
+      if (ALEFELD) {
+        // the midpoint stands in for the phase's own trial point
+        aph = anext == 0 ? 4 : anext;
+        if (aph == 1) aw0 = hi - lo;
+      }
+    } else if (ALEFELD) {
+      aph = anext;
+      const double mid = 0.5 * (lo + hi);
+      if (aph == 0) {
+        g = lo - flo * (hi - lo) / (fhi - flo);
+        aph = 4;
+      } else if (aph == 1) {
+        aw0 = hi - lo;
+        g = NAN;
+        // inverse cubic interpolation through (lo, hi, d, e) at zero when the
+        // four values are finite and pairwise distinct, else the
+        // Newton-quadratic step (two Newton steps on the quadratic through
+        // lo, hi, d)
+        const double xs[4] = {lo, hi, ad, ae}, fs[4] = {flo, fhi, fad, fae};
+        bool distinct = isfinite(fad) && isfinite(fae) && ad == ad && ae == ae;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = i + 1; j < 4; ++j) distinct = distinct && fs[i] != fs[j];
+        if (distinct) {
+          double x = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            double l = xs[i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (j != i) l *= fs[j] / (fs[j] - fs[i]);
+            x += l;
+          }
+          if (x > lo && x < hi) g = x;
+        }
+        if (!(g == g) && isfinite(fad) && ad == ad && ad != lo && ad != hi) {
+          const double fab = (fhi - flo) / (hi - lo);
+          const double fbd = (fad - fhi) / (ad - hi);
+          const double qa = (fbd - fab) / (ad - lo);
+          double x = (qa * flo > 0.0) ? lo : hi;
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const double P = flo + (fab + qa * (x - hi)) * (x - lo);
+            const double dP = fab + qa * (2.0 * x - lo - hi);
+            x -= P / dP;
+          }
+          if (x > lo && x < hi) g = x;
+        }
+        if (!(g == g)) g = lo - flo * (hi - lo) / (fhi - flo);
+      } else if (aph == 2) {
+        // double-length secant from the end with the smaller |phi|, bisection
+        // when it would leave the middle half of the bracket
+        const bool lo_best = fabs(flo) < fabs(fhi);
+        const double uu = lo_best ? lo : hi, fu = lo_best ? flo : fhi;
+        g = uu - 2.0 * fu * (hi - lo) / (fhi - flo);
+        if (fabs(g - uu) > 0.5 * (hi - lo)) g = mid;
+      } else {
+        g = mid;
+      }
     } else if (BRENT) {
       // Brent's step from the better bracket end b towards the other end c:
       // inverse quadratic interpolation through (a, b, c), a the previous b,
@@ -545,7 +658,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 template <int DIM, int N>
 __global__ void __launch_bounds__(256) relax_kernel_brent(const MeshParams mp, const RelaxArgs a) {
   const MeshDims md = dims_of(mp);
-  relax_block<DIM, N, false, true>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB, blockIdx.x, 0);
+  relax_block<DIM, N, false, kRuleBrent>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB,
+                                         blockIdx.x, 0);
+}
+// Alefeld-Potra-Shi trial points (no network guess on this path).
+template <int DIM, int N>
+__global__ void __launch_bounds__(256) relax_kernel_alefeld(const MeshParams mp, const RelaxArgs a) {
+  const MeshDims md = dims_of(mp);
+  relax_block<DIM, N, false, kRuleAlefeld>(mp, md, a, blockIdx.x * RelaxCfg<DIM, N>::EPB,
+                                           blockIdx.x, 0);
 }
 
 // Batched form over (simulation, first element) items; partial per item.
@@ -609,6 +730,9 @@ static hipError_t relax_one(const MeshParams& mp, const RelaxArgs& a, hipStream_
     hipLaunchKernelGGL((relax_kernel<DIM, N, true>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
   else if (a.method == ESRK_ROOT_BRENT)
     hipLaunchKernelGGL((relax_kernel_brent<DIM, N>), dim3(blocks), dim3(C::THREADS), 0, s, mp, a);
+  else if (a.method == ESRK_ROOT_ALEFELD)
+    hipLaunchKernelGGL((relax_kernel_alefeld<DIM, N>), dim3(blocks), dim3(C::THREADS), 0, s, mp,
+                       a);
   else if constexpr (DIM == 3 && C::NPL == 1)
     hipLaunchKernelGGL((relax_kernel_w4<DIM, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, mp,
                        a);

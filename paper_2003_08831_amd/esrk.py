@@ -19,7 +19,7 @@ FP64, FP32_FLUX = 0, 1
 MLP_TRAINED, MLP_MODEL, MLP_IN = 1281, 1298, 5
 SSPRK33, RK44, BSRK43, BSRK85 = 0, 1, 2, 3
 RELAX_LOCAL, RELAX_GLOBAL, RELAX_NONE = 0, 1, 2
-ROOT_ILLINOIS, ROOT_BRENT, ROOT_BISECTION = 0, 1, 2
+ROOT_ILLINOIS, ROOT_BRENT, ROOT_BISECTION, ROOT_ALEFELD = 0, 1, 2, 3
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "EHIP", 3: "ENOMEM", 4: "ENOROOT", 5: "ENONPHYS",
           6: "ENAN", 7: "ENOTSUP"}

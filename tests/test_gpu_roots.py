@@ -1,7 +1,7 @@
 """GPU relaxation root solves with each trial-point rule (Illinois regula
-falsi, Brent, bisection) against the oracle's bisection on the same
-increments; the iteration counts are printed for the comparison the paper
-makes between robust and fast root solvers."""
+falsi, Brent, Alefeld-Potra-Shi, bisection) against the oracle's bisection on
+the same increments; the iteration counts are printed for the comparison the
+paper makes between robust and fast root solvers."""
 import numpy as np
 import pytest
 
@@ -9,6 +9,7 @@ torch = pytest.importorskip("torch")
 
 import oracle as O  # noqa: E402
 from paper_2003_08831_amd import esrk  # noqa: E402
+from paper_2003_08831_amd import inputs as I  # noqa: E402
 from tests.gpu_helpers import ctx_for, dev, host, zeros  # noqa: E402
 from tests.oracle_helpers import orc_mesh  # noqa: E402
 from tests.test_gpu_parity import CASES, check_gammas, make_state  # noqa: E402
@@ -16,7 +17,7 @@ from tests.test_gpu_parity import CASES, check_gammas, make_state  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 METHODS = [(esrk.ROOT_ILLINOIS, "illinois"), (esrk.ROOT_BRENT, "brent"),
-           (esrk.ROOT_BISECTION, "bisection")]
+           (esrk.ROOT_ALEFELD, "alefeld"), (esrk.ROOT_BISECTION, "bisection")]
 
 
 @pytest.mark.parametrize("name,ms,kind", [CASES[0], CASES[2], CASES[4], CASES[7], CASES[9]],
@@ -44,6 +45,41 @@ def test_root_methods_match_oracle(name, ms, kind):
     assert ctx.sync_status()[0] == 0
     with pytest.raises(esrk.EsrkError):
         ctx.set_root_method(9)
+
+
+@pytest.mark.parametrize("problem,frac", [("sod", 0.2), ("sine_shock", 0.3)])
+def test_root_methods_on_shocks(problem, frac):
+    """Increments of one RK(4,4) step across the shocks of the 1-D problems,
+    with dt a fraction of the CFL limit chosen so the shock elements' roots
+    lie far below 1 (Sod: about 0.88, sine-shock: about 0.56): every rule
+    matches the oracle there too."""
+    if problem == "sod":
+        ms = I.sod_mesh(32, 3)
+        u = I.sod_state(ms)
+    else:
+        ms = I.shock_sine_mesh(64, 3)
+        u = I.shock_sine_state(ms)
+    ends = I.end_states(ms, u)
+    m = O.mesh(ms.dim, ms.deg, ms.nel, ms.lo, ms.hi, gas_gamma=ms.gas_gamma, dirichlet=ends)
+    du, deta = O.rk_step(m, O.RK44, u, frac * O.cfl_dt(m, u, 1.0))
+    ref = O.local_relaxation_solve(m, u, du, deta)
+    assert ref["rc"] == 0
+    fin = np.isfinite(ref["gamma_k"])
+    assert ref["gamma_k"][fin].min() < 0.9
+    ctx = ctx_for(ms, tableau=esrk.RK44)
+    counts = {}
+    for method, label in METHODS:
+        ctx.set_root_method(method)
+        gk, gam = zeros(ctx.ne), zeros(1)
+        iters = torch.zeros(ctx.ne, dtype=torch.int32, device="cuda")
+        ctx.local_relaxation_solve(dev(u), dev(du), dev(deta), gk, gam, iters=iters)
+        check_gammas(host(gk), ref)
+        it = host(iters)
+        counts[label] = (it[fin].mean(), it.max())
+        assert it.max() <= (60 if method == esrk.ROOT_BISECTION else 20), label
+    print(f"[root methods {problem}] mean/max phi evaluations per active element: " + ", ".join(
+        f"{k} {v[0]:.2f}/{v[1]}" for k, v in counts.items()))
+    assert ctx.sync_status()[0] == 0
 
 
 def test_root_methods_in_steps():
