@@ -8,9 +8,12 @@ whole locally relaxed RK(4,4) step (4 right-hand sides + stage updates, the
 per-element relaxation solve, the global gamma and the relaxed update), with
 the CFL step size computed on the device.
 
-Metric: DOF-stage updates per second = nodes x RK stages / wall time of the
-step loop (inputs resident in HBM; no host synchronization inside the loop).
-The headline value is the FP64 path; the FP32-flux / FP64-relaxation path is
+Metric: DOF-stage updates per second = nodes x RK stages / time of the step
+loop (inputs resident in HBM; no host synchronization inside the loop).  The
+K timed steps are replayed from one HIP graph recorded by esrk_run_graph (HIP
+events on its stream, device synchronization on both sides); the same K steps
+launched eagerly, one esrk_step call each, are reported beside them.  The
+headline value is the FP64 path; the FP32-flux / FP64-relaxation path is
 reported beside it.  The CPU baseline is the FP64 oracle on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -199,14 +202,31 @@ def run_mode(esrk, I, torch, precision, steps, warmup):
     if rc != 0:
         raise RuntimeError(f"device status {esrk.STATUS.get(rc)} at element {bad}")
     st = stats.cpu().numpy()
-    return ctx, u, dict(ms_total=ms_total, wall_s=wall, N=ctx.N, gamma=float(st[0]),
-                        dt=float(st[1]), t=float(st[2]))
+    # the same K steps recorded into one HIP graph (esrk_run_graph) and
+    # replayed: the first call records and runs them untimed, the second is
+    # timed, with a device synchronization on both sides
+    s = torch.cuda.Stream()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s):
+        ctx.run_graph(u, t, steps, stats, stream=s)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        g0.record(s)
+        ctx.run_graph(u, t, steps, stats, stream=s)
+        g1.record(s)
+    torch.cuda.synchronize()
+    rc, bad = ctx.sync_status()
+    if rc != 0:
+        raise RuntimeError(f"device status {esrk.STATUS.get(rc)} at element {bad}")
+    ms_graph = g0.elapsed_time(g1)
+    return ctx, u, dict(ms_total=ms_total, ms_graph=ms_graph, wall_s=wall, N=ctx.N,
+                        gamma=float(st[0]), dt=float(st[1]), t=float(st[2]))
 
 
 def relax_modes_variant(esrk, I, torch, steps=10, warmup=2):
     """The headline workload (FP64) with each relaxation of esrk_step: none
     (plain RK(4,4)), local (gamma = min_k gamma_k) and global (one gamma for
-    the total entropy; host-driven bracket passes, one stream sync each)."""
+    the total entropy; bracket passes driven on the device)."""
     ms = I.tgv_mesh(NEL, DEG)
     cfg = esrk.make_config(ms.dim, ms.deg, ms.nel, ms.lo, ms.hi, gas_gamma=ms.gas_gamma,
                            precision=esrk.FP64, tableau=esrk.RK44, cfl=0.5)
@@ -351,8 +371,9 @@ def main():
     ctx32, u32, r32 = run_mode(esrk, I, torch, esrk.FP32_FLUX, a.steps, a.warmup)
     N = r64["N"]
     stages = 4 * a.steps
-    val64 = N * stages / (r64["ms_total"] * 1e-3)
-    val32 = N * stages / (r32["ms_total"] * 1e-3)
+    # headline: the K steps replayed from one HIP graph; eager launches beside
+    val64 = N * stages / (r64["ms_graph"] * 1e-3)
+    val32 = N * stages / (r32["ms_graph"] * 1e-3)
 
     kms = time_stage_kernel(esrk, torch, ctx64, u64, a.kernel_reps)
     ne = ctx64.ne
@@ -387,7 +408,7 @@ def main():
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(r64["ms_total"] / a.steps, 4),
+        "ms_per_step": round(r64["ms_graph"] / a.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -397,7 +418,11 @@ def main():
                                "degree 3 (262144 nodes), EC flux differencing + LLF, "
                                "RK(4,4) CFL 0.5, local relaxation",
                    "nodes": N, "stages_timed": stages, "precision": "fp64"},
-        "fp32_flux": {"value": round(val32, 1), "ms_per_step": round(r32["ms_total"] / a.steps, 4),
+        "eager": {"value": round(N * stages / (r64["ms_total"] * 1e-3), 1),
+                  "ms_per_step": round(r64["ms_total"] / a.steps, 4),
+                  "fp32_flux_ms_per_step": round(r32["ms_total"] / a.steps, 4),
+                  "note": "the same K steps launched one esrk_step call at a time"},
+        "fp32_flux": {"value": round(val32, 1), "ms_per_step": round(r32["ms_graph"] / a.steps, 4),
                       "dtype": "f32 flux / f64 relaxation+state", "speedup_vs_fp64":
                       round(val32 / val64, 3)},
         "run": {"gamma_last": r64["gamma"], "dt_last": r64["dt"], "t_end": r64["t"]},

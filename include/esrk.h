@@ -190,10 +190,23 @@ esrk_status esrk_local_relaxation_solve_phi0(esrk_ctx* ctx, const double* u_old,
  * accepted else 0}) are written on the device.  A rejected attempt leaves u
  * and t unchanged (gamma_k = +INF, stats gamma = 1) and only shrinks the
  * proposal.  If the device detects an error, u and t are left unchanged and the
- * status is latched.  No host synchronization (in the default local
- * relaxation mode, see esrk_set_relaxation_mode), no allocation. */
+ * status is latched.  No host synchronization, no allocation, in every
+ * relaxation mode (esrk_set_relaxation_mode). */
 esrk_status esrk_step(esrk_ctx* ctx, double* u, double* t, double dt, double* gamma_k_out,
                       double* stats_out, void* stream);
+
+/* nsteps calls of esrk_step(ctx, u, t, 0 (CFL step size), NULL, stats_out)
+ * recorded once into a HIP graph and replayed on `stream` (not the NULL
+ * stream): the same kernels and arguments as the eager steps, so the same
+ * results bit for bit, with one launch for the whole loop.  The recording is
+ * kept and replayed while u, t, stats_out, nsteps, the stream and the
+ * context's settings are unchanged; any setter call (relaxation mode, root
+ * method, boundary states, error control, step model) makes the next call
+ * record again.  ENOTSUP under error control (the controller's state lives
+ * on the host); EINVAL for NULL u, t or stream or nsteps < 1.  Enqueue only;
+ * device errors are latched as for esrk_step. */
+esrk_status esrk_run_graph(esrk_ctx* ctx, double* u, double* t, int nsteps, double* stats_out,
+                           void* stream);
 
 /* Global relaxation (Sec. 2, the relaxation equation applied to the total
  * entropy instead of each element's): one gamma with

@@ -55,6 +55,15 @@ struct esrk_ctx {
   double* glob_parts = nullptr;       // global relaxation: block partials
   esrk::GlobState* glob_state = nullptr;  // global relaxation: bracket and result
   hipStream_t last = nullptr;
+  // whole steps captured by esrk_run_graph, valid while the pointers, the step
+  // count, the stream and the settings generation match
+  unsigned gen = 0;  // bumped by every setter that changes what a step enqueues
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double *g_u = nullptr, *g_t = nullptr, *g_stats = nullptr;
+  int g_steps = 0;
+  unsigned g_gen = 0;
+  hipStream_t g_stream = nullptr;
 };
 
 namespace {
@@ -351,8 +360,16 @@ esrk_status esrk_create(const esrk_config* cfg, esrk_ctx** out) {
   return ESRK_OK;
 }
 
+static void drop_graph(esrk_ctx* x) {
+  if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
+  if (x->graph) (void)hipGraphDestroy(x->graph);
+  x->gexec = nullptr;
+  x->graph = nullptr;
+}
+
 void esrk_destroy(esrk_ctx* x) {
   if (!x) return;
+  drop_graph(x);
   (void)hipFree(x->ya);
   (void)hipFree(x->yb);
   (void)hipFree(x->du);
@@ -571,6 +588,43 @@ esrk_status esrk_step(esrk_ctx* x, double* u, double* t, double dt, double* gamm
   return hip_status(e);
 }
 
+esrk_status esrk_run_graph(esrk_ctx* x, double* u, double* t, int nsteps, double* stats_out,
+                           void* stream) {
+  if (!x || !u || !t || nsteps < 1 || !stream) return ESRK_EINVAL;
+  // an error-controlled step takes its step size from host-side controller
+  // state, which a recorded graph cannot follow
+  if (x->order_emb > 0 && (x->atol > 0.0 || x->rtol > 0.0)) return ESRK_ENOTSUP;
+  hipStream_t s = (hipStream_t)stream;
+  if (!(x->gexec && x->g_u == u && x->g_t == t && x->g_stats == stats_out &&
+        x->g_steps == nsteps && x->g_stream == s && x->g_gen == x->gen)) {
+    drop_graph(x);
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return ESRK_EHIP;
+    esrk_status st = ESRK_OK;
+    for (int i = 0; i < nsteps && st == ESRK_OK; ++i)
+      st = esrk_step(x, u, t, 0.0, nullptr, stats_out, stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (st != ESRK_OK || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return st != ESRK_OK ? st : ESRK_EHIP;
+    }
+    if (hipGraphInstantiate(&x->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      x->gexec = nullptr;
+      return ESRK_EHIP;
+    }
+    x->graph = g;
+    x->g_u = u;
+    x->g_t = t;
+    x->g_stats = stats_out;
+    x->g_steps = nsteps;
+    x->g_stream = s;
+    x->g_gen = x->gen;
+  }
+  x->last = s;
+  return hipGraphLaunch(x->gexec, s) == hipSuccess ? ESRK_OK : ESRK_EHIP;
+}
+
 esrk_status esrk_set_adaptive(esrk_ctx* x, double atol, double rtol) {
   if (!x || !(atol >= 0.0) || !(rtol >= 0.0) || std::isinf(atol) || std::isinf(rtol))
     return ESRK_EINVAL;
@@ -578,6 +632,7 @@ esrk_status esrk_set_adaptive(esrk_ctx* x, double atol, double rtol) {
   x->atol = atol;
   x->rtol = rtol;
   x->have_dt_next = false;
+  ++x->gen;
   return hip_status(upload_extras(x));
 }
 
@@ -600,6 +655,7 @@ esrk_status esrk_set_dirichlet(esrk_ctx* x, const double* u_left, const double* 
   if (!x || (!u_left) != (!u_right)) return ESRK_EINVAL;
   if (!u_left) {
     x->mp.bc = 0;
+    ++x->gen;
     return ESRK_OK;
   }
   if (x->cfg.dim != 1 || x->cfg.mu > 0.0) return ESRK_ENOTSUP;
@@ -614,6 +670,7 @@ esrk_status esrk_set_dirichlet(esrk_ctx* x, const double* u_left, const double* 
     if (!(q[0] > 0.0) || !(g1 * (q[2] - 0.5 * q[1] * q[1] / q[0]) > 0.0)) return ESRK_ENONPHYS;
   }
   x->mp.bc = 1;
+  ++x->gen;
   return ESRK_OK;
 }
 
@@ -622,6 +679,7 @@ esrk_status esrk_set_root_method(esrk_ctx* x, int method) {
              method != ESRK_ROOT_BISECTION && method != ESRK_ROOT_ALEFELD))
     return ESRK_EINVAL;
   x->root_method = method;
+  ++x->gen;
   return ESRK_OK;
 }
 
@@ -629,6 +687,7 @@ esrk_status esrk_set_relaxation_mode(esrk_ctx* x, int mode) {
   if (!x || (mode != ESRK_RELAX_LOCAL && mode != ESRK_RELAX_GLOBAL && mode != ESRK_RELAX_NONE))
     return ESRK_EINVAL;
   x->relax_mode = mode;
+  ++x->gen;
   return ESRK_OK;
 }
 
@@ -674,6 +733,7 @@ esrk_status esrk_set_step_model(esrk_ctx* x, const float* model, float* feats_ou
   if (!x) return ESRK_EINVAL;
   x->step_model = model;
   x->step_feats = feats_out;
+  ++x->gen;
   return ESRK_OK;
 }
 

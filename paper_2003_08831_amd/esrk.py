@@ -80,6 +80,8 @@ def load():
     L.esrk_local_relaxation_solve.restype = st
     L.esrk_step.argtypes = [vp, vp, vp, dp, vp, vp, vp]
     L.esrk_step.restype = st
+    L.esrk_run_graph.argtypes = [vp, vp, vp, C.c_int, vp, vp]
+    L.esrk_run_graph.restype = st
     L.esrk_global_relaxation_solve.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_int), vp]
     L.esrk_global_relaxation_solve.restype = st
     L.esrk_set_relaxation_mode.argtypes = [vp, C.c_int]
@@ -278,6 +280,12 @@ class Context:
             raise ValueError("stats needs 8 float64 entries")
         _check(load().esrk_step(self._h, _ptr(u), _ptr(t), float(dt), _ptr(gamma_k),
                                 _ptr(stats), _stream(stream)), "esrk_step")
+
+    def run_graph(self, u, t, nsteps, stats=None, stream=None):
+        if stats is not None and not isinstance(stats, int) and stats.numel() < 8:
+            raise ValueError("stats needs 8 float64 entries")
+        _check(load().esrk_run_graph(self._h, _ptr(u), _ptr(t), int(nsteps), _ptr(stats),
+                                     _stream(stream)), "esrk_run_graph")
 
     def sync_status(self):
         bad = C.c_int64(-1)
