@@ -41,6 +41,7 @@ class Mesh(C.Structure):
         ("volume_flux", C.c_int),
         ("bc", C.c_int),
         ("ubc", C.c_double * 10),
+        ("bckind", C.c_int * 2),
     ]
 
 
@@ -130,9 +131,12 @@ def _p(a):
 
 
 def mesh(dim, deg, nel, lo, hi, gas_gamma=1.4, gas_r=1.0, mu=0.0, prandtl=0.72,
-         lambda_scale=1.0, volume_flux=0, dirichlet=None) -> Mesh:
+         lambda_scale=1.0, volume_flux=0, dirichlet=None, outflow=(False, False)) -> Mesh:
     """dirichlet = (u_left, u_right) conserved exterior states (1-D): Dirichlet
-    boundaries at both ends instead of periodic ones."""
+    boundaries at both ends instead of periodic ones.  outflow = (left, right):
+    an end marked True takes its interior trace as the exterior state (its
+    entry of dirichlet is then unused and may be None; outflow alone makes
+    the mesh non-periodic)."""
     m = Mesh()
     m.dim, m.deg = dim, deg
     nel = list(nel) + [1] * (3 - len(nel))
@@ -143,9 +147,12 @@ def mesh(dim, deg, nel, lo, hi, gas_gamma=1.4, gas_r=1.0, mu=0.0, prandtl=0.72,
     m.gas_gamma, m.gas_r, m.mu, m.prandtl = gas_gamma, gas_r, mu, prandtl
     m.lambda_scale, m.volume_flux = lambda_scale, volume_flux
     m.bc = 0
-    if dirichlet is not None:
+    if dirichlet is not None or any(outflow):
         m.bc = 1
         for s in range(2):
+            m.bckind[s] = 1 if outflow[s] else 0
+            if outflow[s]:
+                continue
             st = list(dirichlet[s]) + [0.0] * (5 - len(dirichlet[s]))
             for v in range(5):
                 m.ubc[5 * s + v] = float(st[v])

@@ -44,8 +44,10 @@ typedef struct {
   double prandtl;       /* Prandtl number */
   double lambda_scale;  /* interface dissipation scale: 1 = local Lax-Friedrichs, 0 = EC */
   int volume_flux;      /* 0 = entropy-conservative (Chandrashekar), 1 = central average */
-  int bc;               /* 0 = periodic; 1 = Dirichlet at both ends (1-D Euler only) */
+  int bc;               /* 0 = periodic; 1 = boundaries at both ends (1-D Euler only) */
   double ubc[2][5];     /* Dirichlet exterior states (conserved), [0] left, [1] right */
+  int bckind[2];        /* per end: 0 = Dirichlet (exterior state ubc), 1 = outflow
+                           (exterior state = the interior trace, so the SAT vanishes) */
 } orc_mesh;
 
 /* ---- summation-by-parts operators on Lobatto nodes (Sec. 3.1) ---- */

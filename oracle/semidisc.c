@@ -44,6 +44,8 @@ static int setup(const orc_mesh* g, geom* G) {
   if (g->dim < 1 || g->dim > 3 || g->deg < 1 || g->deg > 15) return ORC_EINVAL;
   /* Dirichlet boundaries: 1-D Euler only */
   if (g->bc != 0 && (g->bc != 1 || g->dim != 1 || g->mu > 0.0)) return ORC_EINVAL;
+  if (g->bc && (g->bckind[0] < 0 || g->bckind[0] > 1 || g->bckind[1] < 0 || g->bckind[1] > 1))
+    return ORC_EINVAL;
   G->bc = g->bc;
   G->dim = g->dim;
   G->n = g->deg + 1;
@@ -186,8 +188,8 @@ static void surface_term(const orc_mesh* g, const geom* G, const double* u, doub
       for (int m = 0; m < G->dim; ++m) {
         if (im[m] == p) { /* this node is the left state of the +m interface */
           long kn = neighbour(G, k, m, +1);
-          if (kn < 0)
-            for (int v = 0; v < G->nv; ++v) un[v] = g->ubc[1][v]; /* right boundary */
+          if (kn < 0) /* right boundary: given state, or the trace itself (outflow) */
+            for (int v = 0; v < G->nv; ++v) un[v] = g->bckind[1] ? ui[v] : g->ubc[1][v];
           else
             gather(G, u, kn * G->nd + node_with(G, i, m, 0), un);
           interface_flux(g, m, ui, un, fs);
@@ -197,8 +199,8 @@ static void surface_term(const orc_mesh* g, const geom* G, const double* u, doub
         }
         if (im[m] == 0) { /* right state of the -m interface */
           long kn = neighbour(G, k, m, -1);
-          if (kn < 0)
-            for (int v = 0; v < G->nv; ++v) un[v] = g->ubc[0][v]; /* left boundary */
+          if (kn < 0) /* left boundary */
+            for (int v = 0; v < G->nv; ++v) un[v] = g->bckind[0] ? ui[v] : g->ubc[0][v];
           else
             gather(G, u, kn * G->nd + node_with(G, i, m, p), un);
           interface_flux(g, m, un, ui, fs);
