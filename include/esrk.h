@@ -269,6 +269,22 @@ esrk_status esrk_error_estimate(esrk_ctx* ctx, double* err, double* norm, void* 
  * that follow. */
 esrk_status esrk_set_dirichlet(esrk_ctx* ctx, const double* u_left, const double* u_right);
 
+/* Boundary kinds of the two ends of a 1-D Euler context (Sec. 4, 1-D
+ * problems: the ends are imposed weakly through the interface flux, as the
+ * paper imposes its boundary data by penalizing against a given state).
+ * ESRK_BC_DIRICHLET: the end's exterior state is u_* (3 conserved values).
+ * ESRK_BC_OUTFLOW: the exterior state is the end's own interior trace, so the
+ * interface flux there is the trace's physical flux (u_* is ignored and may
+ * be NULL).  esrk_set_dirichlet(ctx, l, r) is esrk_set_boundaries(ctx,
+ * DIRICHLET, l, DIRICHLET, r); esrk_set_dirichlet(ctx, NULL, NULL) makes the
+ * mesh periodic again.  ENOTSUP for dim != 1 or a Navier-Stokes context;
+ * EINVAL for another kind, a NULL or non-finite Dirichlet state; ENONPHYS for
+ * a Dirichlet state with rho <= 0 or p <= 0.  Nothing changes on an error.
+ * Applies to the calls that follow. */
+enum { ESRK_BC_DIRICHLET = 0, ESRK_BC_OUTFLOW = 1 };
+esrk_status esrk_set_boundaries(esrk_ctx* ctx, int kind_left, const double* u_left,
+                                int kind_right, const double* u_right);
+
 /* Root-solve method of the local relaxation (Sec. 4 names Brent's method and
  * the first method of Alefeld, Potra and Shi as robust, secant and Newton as
  * slightly faster): ESRK_ROOT_ILLINOIS (default: regula falsi with the

@@ -651,6 +651,34 @@ esrk_status esrk_error_estimate(esrk_ctx* x, double* err, double* norm, void* st
   return hip_status(e);
 }
 
+esrk_status esrk_set_boundaries(esrk_ctx* x, int kind_left, const double* u_left,
+                                int kind_right, const double* u_right) {
+  if (!x) return ESRK_EINVAL;
+  if (x->cfg.dim != 1 || x->cfg.mu > 0.0) return ESRK_ENOTSUP;
+  const int kind[2] = {kind_left, kind_right};
+  const double* ext[2] = {u_left, u_right};
+  double ubc[2][5] = {};
+  const double g1 = x->cfg.gas_gamma - 1.0;
+  // validate both ends before changing anything
+  for (int s = 0; s < 2; ++s) {
+    if (kind[s] == ESRK_BC_OUTFLOW) continue;
+    if (kind[s] != ESRK_BC_DIRICHLET || !ext[s]) return ESRK_EINVAL;
+    for (int v = 0; v < 3; ++v) {
+      if (!std::isfinite(ext[s][v])) return ESRK_EINVAL;
+      ubc[s][v] = ext[s][v];
+    }
+    const double* q = ubc[s];
+    if (!(q[0] > 0.0) || !(g1 * (q[2] - 0.5 * q[1] * q[1] / q[0]) > 0.0)) return ESRK_ENONPHYS;
+  }
+  for (int s = 0; s < 2; ++s) {
+    for (int v = 0; v < 5; ++v) x->mp.ubc[s][v] = ubc[s][v];
+    x->mp.bckind[s] = kind[s] == ESRK_BC_OUTFLOW ? 1 : 0;
+  }
+  x->mp.bc = 1;
+  ++x->gen;
+  return ESRK_OK;
+}
+
 esrk_status esrk_set_dirichlet(esrk_ctx* x, const double* u_left, const double* u_right) {
   if (!x || (!u_left) != (!u_right)) return ESRK_EINVAL;
   if (!u_left) {
@@ -658,20 +686,7 @@ esrk_status esrk_set_dirichlet(esrk_ctx* x, const double* u_left, const double* 
     ++x->gen;
     return ESRK_OK;
   }
-  if (x->cfg.dim != 1 || x->cfg.mu > 0.0) return ESRK_ENOTSUP;
-  for (int v = 0; v < 3; ++v) {
-    if (!std::isfinite(u_left[v]) || !std::isfinite(u_right[v])) return ESRK_EINVAL;
-    x->mp.ubc[0][v] = u_left[v];
-    x->mp.ubc[1][v] = u_right[v];
-  }
-  const double g1 = x->cfg.gas_gamma - 1.0;
-  for (int s = 0; s < 2; ++s) {
-    const double* q = x->mp.ubc[s];
-    if (!(q[0] > 0.0) || !(g1 * (q[2] - 0.5 * q[1] * q[1] / q[0]) > 0.0)) return ESRK_ENONPHYS;
-  }
-  x->mp.bc = 1;
-  ++x->gen;
-  return ESRK_OK;
+  return esrk_set_boundaries(x, ESRK_BC_DIRICHLET, u_left, ESRK_BC_DIRICHLET, u_right);
 }
 
 esrk_status esrk_set_root_method(esrk_ctx* x, int method) {

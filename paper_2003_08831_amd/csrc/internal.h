@@ -53,8 +53,9 @@ struct MeshParams {
   double gg;                 // ratio of specific heats
   double lambda_scale;
   double cfl, hmin;
-  int bc;             // 0 periodic, 1 Dirichlet (1-D Euler)
+  int bc;             // 0 periodic, 1 boundaries at both ends (1-D Euler)
   double ubc[2][5];   // Dirichlet exterior states (conserved): [0] left, [1] right
+  int bckind[2];      // per end: 0 Dirichlet (ubc), 1 outflow (exterior = interior trace)
 };
 
 // The per-mesh part of MeshParams (differs between the simulations of a batch).
@@ -64,7 +65,7 @@ struct MeshDims {
   double two_over_h[3];
   double half_h[3];
   double hmin, cfl;
-  int bc;  // 0 periodic, 1 Dirichlet at both ends of direction 0 (1-D)
+  int bc;  // 0 periodic, 1 boundaries at both ends of direction 0 (1-D)
 };
 __host__ __device__ inline MeshDims dims_of(const MeshParams& mp) {
   MeshDims d;

@@ -100,7 +100,7 @@ __device__ __forceinline__ int neighbour(const MeshDims& md, int k, int m, int d
   int cm = (m == 0) ? c[0] : (m == 1) ? c[1] : c[2];
   const int nm = (m == 0) ? md.nel[0] : (m == 1) ? md.nel[1] : md.nel[2];
   cm += dir;
-  if (md.bc && (cm < 0 || cm >= nm)) return -1;  // Dirichlet boundary face
+  if (md.bc && (cm < 0 || cm >= nm)) return -1;  // boundary face
   cm = (cm < 0) ? cm + nm : (cm >= nm ? cm - nm : cm);
   if (m == 0) c[0] = cm;
   if (m == 1) c[1] = cm;
@@ -318,7 +318,8 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       const int kn = snbr[e * 2 * DIM + 2 * m + side];
       const int own = base + (side ? (N - 1) * stride : 0);
       const int nbr = base + (side ? 0 : (N - 1) * stride);
-      // a Dirichlet boundary face (1-D) takes the exterior state from mp.ubc
+      // a boundary face (1-D) takes the exterior state from mp.ubc (Dirichlet)
+      // or from the own trace (outflow: f* is then the trace's physical flux)
       const bool bnd = kn < 0;
       const int gL = side ? k * ND + own : (bnd ? 0 : kn * ND + nbr);
       const int gR = side ? (bnd ? 0 : kn * ND + nbr) : k * ND + own;
@@ -331,10 +332,11 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       }
       if constexpr (DIM == 1) {
         if (bnd) {
+          const bool outflow = mp.bckind[side] != 0;
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            if (side) qr[v] = T(mp.ubc[1][v]);
-            else ql[v] = T(mp.ubc[0][v]);
+            if (side) qr[v] = outflow ? ql[v] : T(mp.ubc[1][v]);
+            else ql[v] = outflow ? qr[v] : T(mp.ubc[0][v]);
           }
         }
       }

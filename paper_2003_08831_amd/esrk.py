@@ -20,6 +20,7 @@ MLP_TRAINED, MLP_MODEL, MLP_IN = 1281, 1298, 5
 SSPRK33, RK44, BSRK43, BSRK85 = 0, 1, 2, 3
 RELAX_LOCAL, RELAX_GLOBAL, RELAX_NONE = 0, 1, 2
 ROOT_ILLINOIS, ROOT_BRENT, ROOT_BISECTION, ROOT_ALEFELD = 0, 1, 2, 3
+BC_DIRICHLET, BC_OUTFLOW = 0, 1
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "EHIP", 3: "ENOMEM", 4: "ENOROOT", 5: "ENONPHYS",
           6: "ENAN", 7: "ENOTSUP"}
@@ -92,6 +93,9 @@ def load():
     L.esrk_local_relaxation_solve_phi0.restype = st
     L.esrk_set_dirichlet.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.esrk_set_dirichlet.restype = st
+    L.esrk_set_boundaries.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.c_int,
+                                      C.POINTER(C.c_double)]
+    L.esrk_set_boundaries.restype = st
     L.esrk_set_root_method.argtypes = [vp, C.c_int]
     L.esrk_set_root_method.restype = st
     L.esrk_set_adaptive.argtypes = [vp, dp, dp]
@@ -258,6 +262,17 @@ class Context:
                 return None
             return (C.c_double * 3)(*[float(v) for v in x])
         _check(load().esrk_set_dirichlet(self._h, arr(u_left), arr(u_right)), "esrk_set_dirichlet")
+
+    def set_boundaries(self, kind_left, u_left, kind_right, u_right):
+        """Boundary kind (BC_DIRICHLET, BC_OUTFLOW) and Dirichlet state (3
+        conserved values, host; None for an outflow end) of each end of a
+        1-D context."""
+        def arr(x):
+            if x is None:
+                return None
+            return (C.c_double * 3)(*[float(v) for v in x])
+        _check(load().esrk_set_boundaries(self._h, int(kind_left), arr(u_left), int(kind_right),
+                                          arr(u_right)), "esrk_set_boundaries")
 
     def set_root_method(self, method):
         _check(load().esrk_set_root_method(self._h, int(method)), "esrk_set_root_method")

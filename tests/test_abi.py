@@ -47,6 +47,7 @@ def test_create_rejects_empty_mesh_and_null():
     assert esrk.load().esrk_rhs_euler(None, None, None, None, None) == 1
     assert esrk.load().esrk_step(None, None, None, 0.0, None, None, None) == 1
     assert esrk.load().esrk_run_graph(None, None, None, 1, None, None) == 1
+    assert esrk.load().esrk_set_boundaries(None, 1, None, 1, None) == 1
 
 
 def test_create_rejects_meshes_beyond_32_bit_indexing():

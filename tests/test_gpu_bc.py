@@ -44,6 +44,82 @@ def test_dirichlet_rhs_parity(deg):
     assert rhs_close(host(out), O.rhs(O.mesh(1, deg, ms.nel, ms.lo, ms.hi), u)[0], ms, S) <= 1.0
 
 
+@pytest.mark.parametrize("deg", [3, 5])
+@pytest.mark.parametrize("kinds", [(True, True), (False, True), (True, False)],
+                         ids=["outflow_both", "dirichlet_outflow", "outflow_dirichlet"])
+def test_outflow_rhs_parity(deg, kinds):
+    ms = I.MeshSpec(dim=1, deg=deg, nel=(11, 1, 1), lo=(-1, 0, 0), hi=(2, 1, 1))
+    u = I.random_state(ms, seed=19, smooth=True)
+    states = (np.array([1.2, 0.3, 2.9]), np.array([0.8, -0.1, 2.1]))
+    ext = tuple(None if kinds[s] else states[s] for s in range(2))
+    m = O.mesh(1, deg, ms.nel, ms.lo, ms.hi, gas_gamma=ms.gas_gamma, dirichlet=ext,
+               outflow=kinds)
+    ref = O.rhs(m, u)[0]
+    ctx = ctx_for(ms)
+    kind = [esrk.BC_OUTFLOW if k else esrk.BC_DIRICHLET for k in kinds]
+    ctx.set_boundaries(kind[0], ext[0], kind[1], ext[1])
+    out, eta = zeros(u.size), zeros(ctx.ne)
+    ctx.rhs_euler(dev(u), out, eta)
+    S = term_scale(O, ms, u)
+    assert rhs_close(host(out), ref, ms, S) <= 1.0
+    assert ctx.sync_status()[0] == 0
+
+
+def test_outflow_relaxed_steps_parity():
+    """Five locally relaxed RK(4,4) steps of the sine-shock state (64
+    elements, p = 3) with outflow ends against the oracle."""
+    ms = I.shock_sine_mesh(64, 3)
+    u = I.shock_sine_state(ms)
+    m = O.mesh(1, 3, ms.nel, ms.lo, ms.hi, gas_gamma=ms.gas_gamma, outflow=(True, True))
+    ctx = ctx_for(ms, tableau=esrk.RK44)
+    ctx.set_boundaries(esrk.BC_OUTFLOW, None, esrk.BC_OUTFLOW, None)
+    dt = 0.1 * O.cfl_dt(m, u, 1.0)
+    ud, t, st = dev(u), zeros(1), zeros(8)
+    for step in range(5):
+        du, deta, a = O.rk_step_a(m, O.RK44, u, dt)
+        ref = O.local_relaxation_solve(m, u, du, deta, a=a)
+        assert ref["rc"] == 0
+        g = ref["gamma"]
+        fin = np.isfinite(ref["gamma_k"])
+        gtol = 2e-12
+        if fin.any():
+            k = np.argmin(np.where(fin, ref["gamma_k"], np.inf))
+            gtol += 1e-3 * ref["noise"][k] / ref["curv"][k]
+        ctx.step(ud, t, dt, None, st)
+        assert abs(host(st)[0] - g) <= gtol, (step, host(st)[0], g)
+        u = u + g * du
+        got = host(ud).reshape(3, -1)
+        for v in range(3):
+            uv = u.reshape(3, -1)[v]
+            tolv = 1e-12 * np.abs(uv).max() + gtol * np.abs(du.reshape(3, -1)[v]).max()
+            assert np.abs(got[v] - uv).max() <= tolv, (step, v)
+        ud.copy_(dev(u))
+    assert ctx.sync_status()[0] == 0
+
+
+def test_boundary_rejections_change_nothing():
+    ms = I.sod_mesh(8, 3)
+    u = dev(I.sod_state(ms))
+    ctx = ctx_for(ms)
+    left, right = [1.0, 0.0, 2.5], [0.125, 0.0, 0.25]
+    ctx.set_boundaries(esrk.BC_DIRICHLET, left, esrk.BC_OUTFLOW, None)
+    a, b = zeros(u.numel()), zeros(u.numel())
+    ctx.rhs_euler(u, a)
+    for args, code in (((7, left, esrk.BC_OUTFLOW, None), 1),
+                       ((esrk.BC_DIRICHLET, None, esrk.BC_OUTFLOW, None), 1),
+                       ((esrk.BC_OUTFLOW, None, esrk.BC_DIRICHLET, [1.0, 0.0, -2.5]), 5),
+                       ((esrk.BC_DIRICHLET, [float("nan"), 0, 1], esrk.BC_OUTFLOW, None), 1)):
+        with pytest.raises(esrk.EsrkError) as e:
+            ctx.set_boundaries(*args)
+        assert e.value.code == code
+    ctx.rhs_euler(u, b)
+    assert torch.equal(a, b)
+    ctx2 = ctx_for(I.vortex_mesh(4, 3))
+    with pytest.raises(esrk.EsrkError) as e:
+        ctx2.set_boundaries(esrk.BC_OUTFLOW, None, esrk.BC_OUTFLOW, None)
+    assert e.value.code == 7
+
+
 def test_dirichlet_rejections():
     ctx = ctx_for(I.vortex_mesh(4, 3))
     with pytest.raises(esrk.EsrkError) as e:
