@@ -1,6 +1,7 @@
 """The C-ABI library loads and exports every entry point include/esrk.h
 declares; argument validation needs no GPU (CPU only, no compute calls)."""
 import ctypes as C
+import os
 import subprocess
 
 import pytest
@@ -107,3 +108,22 @@ def test_error_control_entry_point_validation():
     assert L.esrk_set_dirichlet(None, None, None) == 1
     assert L.esrk_local_relaxation_solve_phi0(None, None, None, None, None, None, None, None,
                                               None) == 1
+
+
+def test_missing_library_fails_loudly():
+    """Without the built HIP library every entry point raises (no CPU path)."""
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2003_08831_amd import esrk\n"
+        "esrk.LIB_PATH = '/nonexistent/libesrk.so'\n"
+        "try:\n"
+        "    esrk.Context(esrk.make_config(2, 3, (4, 4), (0, 0), (1, 1)))\n"
+        "except RuntimeError as e:\n"
+        "    print('raised:', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(3)\n" % os.path.dirname(esrk.HERE)
+    )
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "HIP library missing" in r.stdout
