@@ -48,7 +48,15 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // dimension (groups of 4).  v_mfma_f32_4x4x1f32 with 16 blocks: lane 4b + t
 // supplies A = row 64 g + 4b + t and B = D[4 c0 + t][j]; it receives rows
 // 64 g + 4b + (0..3) of output column 4 c0 + t.  Every lane of a wave takes
-// part (out-of-range rows and columns are zero-padded).
+// part (out-of-range rows and columns are zero-padded).  out may equal in
+// (with in_dstride = NV E ND the layouts agree): each row is read by its own
+// lane before the results of that row are written, and rows are disjoint.
+// Value of lane Q of this lane's quad (all four lanes of the quad active).
+template <int Q>
+__device__ __forceinline__ int quad_bcast(int v) {
+  return __builtin_amdgcn_mov_dpp(v, Q * 0x55, 0xF, 0xF, false);
+}
+
 template <int DIM, int N, int E, int NV>
 __device__ __forceinline__ void dapply_mfma(const float* in, int in_dstride, float* out,
                                             const double* D2, int nthreads) {
@@ -70,9 +78,11 @@ __device__ __forceinline__ void dapply_mfma(const float* in, int in_dstride, flo
       B[c][j] = i < N ? float(0.5 * D2[i * N + j]) : 0.f;
     }
   for (int g = wave; g < G; g += nw) {
-    // this lane's A row
+    // this lane's A row: its input line and, for the output, the offset of
+    // the line's first node and the node stride (-1: row beyond R)
     const int row = 64 * g + lane;
     float x[N];
+    int obase, ostride;
     {
       const bool ok = row < R;
       const int rr = ok ? row : 0;
@@ -86,27 +96,24 @@ __device__ __forceinline__ void dapply_mfma(const float* in, int in_dstride, flo
       const float* src = in + d * in_dstride + (v * E + e) * ND + base;
 #pragma unroll
       for (int j = 0; j < N; ++j) x[j] = ok ? src[j * stride] : 0.f;
+      obase = ok ? ev * ND + base : -1;
+      ostride = stride;
     }
+    // output row 64 g + (lane & ~3) + q is the A row of quad lane q: its
+    // offsets come from that lane by a quad broadcast (DPP quad_perm)
+    const int ob[4] = {quad_bcast<0>(obase), quad_bcast<1>(obase), quad_bcast<2>(obase),
+                       quad_bcast<3>(obase)};
+    const int os[4] = {quad_bcast<0>(ostride), quad_bcast<1>(ostride), quad_bcast<2>(ostride),
+                       quad_bcast<3>(ostride)};
 #pragma unroll
     for (int c = 0; c < CG; ++c) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int j = 0; j < N; ++j) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(x[j], B[c][j], acc, 0, 0, 0);
       const int i = 4 * c + t;
-      if (i < N) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int ro = 64 * g + (lane & ~3) + q;
-          if (ro < R) {
-            const int l = ro % NL;
-            const int ev = ro / NL;
-            const int d = (ev / E) / NV;
-            const int stride = (d == 0) ? 1 : (d == 1) ? N : N * N;
-            const int base = (l % stride) + (l / stride) * stride * N;
-            out[ev * ND + base + i * stride] = acc[q];
-          }
-        }
-      }
+      for (int q = 0; q < 4; ++q)
+        if (i < N && ob[q] >= 0) out[ob[q] + i * os[q]] = acc[q];
     }
   }
 }
@@ -370,8 +377,10 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
   }
   __syncthreads();
   if constexpr (kUseMfma<T>) {
-    __shared__ float sout[DIM * NV * E * ND];
-    dapply_mfma<DIM, N, E, NV>(sg, NV * E * ND, sout, mp.D2, G::THREADS);
+    // in place: a row's line values are read (by the lane that owns the row)
+    // before its results overwrite them, and rows cover disjoint LDS slots,
+    // so the block needs no second LDS buffer (more resident blocks)
+    dapply_mfma<DIM, N, E, NV>(sg, NV * E * ND, sg, mp.D2, G::THREADS);
     __syncthreads();
     if (valid) {
       const long long gi = (long long)k * ND + i;
@@ -381,7 +390,7 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
           acc += mp.two_over_h[d] *
-                 double(sout[(d * NV + v) * E * ND + e * ND + i] + lift[d][v]);
+                 double(sg[(d * NV + v) * E * ND + e * ND + i] + lift[d][v]);
         visc[v * Ntot + gi] = acc;
       }
     }
