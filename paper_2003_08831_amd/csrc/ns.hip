@@ -314,12 +314,27 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
     dsum *= M;
   }
   if (diss) {
-    if (tid < E * ND) sd[tid] = valid ? dsum : 0.0;
-    __syncthreads();
-    if (valid && i == 0) {
-      double s = 0.0;
-      for (int q2 = 0; q2 < ND; ++q2) s += sd[e * ND + q2];
-      diss[k] = s;
+    if constexpr (E == 1) {
+      // one element per block: butterfly sums within each wave, then the
+      // waves' partials in wave order
+      double s = valid ? dsum : 0.0;
+#pragma unroll
+      for (int off = 32; off >= 1; off /= 2) s += __shfl_xor(s, off, 64);
+      if ((tid & 63) == 0) sd[tid >> 6] = s;
+      __syncthreads();
+      if (tid == 0 && k < mp.ne) {
+        double t = 0.0;
+        for (int w = 0; w < G::THREADS / 64; ++w) t += sd[w];
+        diss[k] = t;
+      }
+    } else {
+      if (tid < E * ND) sd[tid] = valid ? dsum : 0.0;
+      __syncthreads();
+      if (valid && i == 0) {
+        double s = 0.0;
+        for (int q2 = 0; q2 < ND; ++q2) s += sd[e * ND + q2];
+        diss[k] = s;
+      }
     }
   }
 }
