@@ -231,6 +231,32 @@ def test_tgv16_p3_50_free_steps_conservation_and_entropy(tgv16):
     assert ctx.sync_status()[0] == 0
 
 
+@pytest.mark.parametrize("precision,tol", [(esrk.FP64, 1e-13), (esrk.FP32_FLUX, 1e-5)],
+                         ids=["fp64", "fp32_flux"])
+def test_tgv16_p3_3000_graph_replayed_steps(tgv16, precision, tol):
+    """3000 relaxed RK(4,4) steps (t = 4.7) replayed from a recorded graph of
+    100 steps: no latched error, every sampled gamma in (0.999, 1], conserved
+    integrals kept to tol of sum M|u| (FP32 flux: the stated 1e-5 bound)."""
+    ms, m, u0, _, _ = tgv16
+    ctx = ctx_for(ms, tableau=esrk.RK44, cfl=0.5, precision=precision)
+    ud, t, stats = dev(u0), zeros(1), zeros(8)
+    M = node_mass(O, ms)
+    cons0 = (view(ms, u0) * M).sum(axis=(1, 2))
+    sc = (np.abs(view(ms, u0)) * M).sum(axis=(1, 2))
+    sc[1:4] = sc[1:4].sum()  # one momentum scale (the z-momentum is zero)
+    s = torch.cuda.Stream()
+    for _ in range(30):
+        with torch.cuda.stream(s):
+            ctx.run_graph(ud, t, 100, stats, stream=s)
+        s.synchronize()
+        assert ctx.sync_status()[0] == 0
+        g = host(stats)[0]
+        assert 0.999 < g <= 1.0, g
+    assert host(t)[0] > 4.5
+    cons = (view(ms, host(ud)) * M).sum(axis=(1, 2))
+    assert np.all(np.abs(cons - cons0) <= tol * sc), np.abs(cons - cons0) / sc
+
+
 def test_ns_tgv32_p4_rhs_and_dissipation():
     ms = I.tgv_mesh(32, 4, mu=1.0 / 1600.0)
     u = I.tgv_state(ms, 0.1)
