@@ -351,7 +351,7 @@ def cpu_baseline(I, steps):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
