@@ -332,7 +332,7 @@ __device__ __forceinline__ void rhs_block(const MeshParams& mp, const MeshDims& 
       }
       if constexpr (DIM == 1) {
         if (bnd) {
-          const bool outflow = mp.bckind[side] != 0;
+          const bool outflow = (side ? mp.bckind[1] : mp.bckind[0]) != 0;
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             if (side) qr[v] = outflow ? ql[v] : T(mp.ubc[1][v]);
