@@ -30,6 +30,11 @@ CASES = [
     ("d3p3_tgv", I.tgv_mesh(3, 3), "tgv"),
     ("d3p3_rand", I.MeshSpec(dim=3, deg=3, nel=(3, 3, 3), lo=(0, 0, 0), hi=(1, 1, 1)), "rand"),
     ("d3p4", I.MeshSpec(dim=3, deg=4, nel=(3, 2, 3), lo=(0, 0, 0), hi=(1, 1, 1)), "smooth"),
+    # the ends of the degree range: 3-D p5 (216 nodes per element, two nodes per
+    # thread in the stage epilogue, four per lane in the relaxation), 3-D p1, 1-D p5
+    ("d3p5", I.MeshSpec(dim=3, deg=5, nel=(2, 2, 3), lo=(0, 0, 0), hi=(1, 1, 1.5)), "smooth"),
+    ("d3p1", I.MeshSpec(dim=3, deg=1, nel=(4, 3, 2), lo=(0, 0, 0), hi=(1, 1, 1)), "rand"),
+    ("d1p5", I.MeshSpec(dim=1, deg=5, nel=(9, 1, 1), lo=(0, 0, 0), hi=(2, 1, 1)), "smooth"),
 ]
 
 
@@ -158,8 +163,10 @@ def check_gammas(gk_gpu, ref):
 
 
 @pytest.mark.parametrize("tab", [esrk.SSPRK33, esrk.RK44], ids=["ssprk33", "rk44"])
-@pytest.mark.parametrize("name,ms,kind", [CASES[0], CASES[2], CASES[5], CASES[7], CASES[9]],
-                         ids=["d1p3", "d2p3_vortex", "d2p5", "d3p3_tgv", "d3p4"])
+@pytest.mark.parametrize("name,ms,kind", [CASES[0], CASES[2], CASES[5], CASES[7], CASES[9],
+                                          CASES[10], CASES[11], CASES[12]],
+                         ids=["d1p3", "d2p3_vortex", "d2p5", "d3p3_tgv", "d3p4", "d3p5", "d3p1",
+                              "d1p5"])
 def test_local_relaxation_solve_parity(tab, name, ms, kind):
     u = make_state(ms, kind, seed=3)
     m = orc_mesh(O, ms)
@@ -231,8 +238,8 @@ def oracle_step(m, tab, u, t, cfl):
 
 
 @pytest.mark.parametrize("tab", [esrk.SSPRK33, esrk.RK44], ids=["ssprk33", "rk44"])
-@pytest.mark.parametrize("name,ms,kind", [CASES[0], CASES[2], CASES[7]],
-                         ids=["d1p3", "d2p3_vortex", "d3p3_tgv"])
+@pytest.mark.parametrize("name,ms,kind", [CASES[0], CASES[2], CASES[7], CASES[10], CASES[12]],
+                         ids=["d1p3", "d2p3_vortex", "d3p3_tgv", "d3p5", "d1p5"])
 def test_step_parity(tab, name, ms, kind):
     """Whole locally relaxed steps with the device CFL step size, started from
     the oracle's state at each of five successive steps: dt, gamma, relaxed
