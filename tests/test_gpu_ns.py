@@ -22,6 +22,9 @@ CASES = [
      "smooth"),
     ("d1p3", I.MeshSpec(dim=1, deg=3, nel=(11, 1, 1), lo=(0, 0, 0), hi=(1, 1, 1), mu=0.03),
      "smooth"),
+    # 3-D p5: 216 nodes per element (four waves per block), nine MFMA row groups
+    ("d3p5", I.MeshSpec(dim=3, deg=5, nel=(2, 2, 2), lo=(0, 0, 0), hi=(1, 1, 1), mu=0.01),
+     "smooth"),
 ]
 IDS = [c[0] for c in CASES]
 
@@ -111,7 +114,8 @@ def test_ns_stage_chain_and_step_parity(tab, name, ms, kind):
     assert ctx.sync_status()[0] == 0
 
 
-@pytest.mark.parametrize("name,ms,kind", [CASES[0], CASES[2]], ids=["d2p3", "d3p3_tgv"])
+@pytest.mark.parametrize("name,ms,kind", [CASES[0], CASES[2], CASES[3], CASES[5]],
+                         ids=["d2p3", "d3p3_tgv", "d3p4", "d3p5"])
 def test_ns_fp32_conservation(name, ms, kind):
     u = state(ms, kind)
     m = orc_mesh(O, ms)
