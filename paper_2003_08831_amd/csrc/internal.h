@@ -67,6 +67,17 @@ struct MeshDims {
   double hmin, cfl;
   int bc;  // 0 periodic, 1 boundaries at both ends of direction 0 (1-D)
 };
+// Work item of block b of nb.  The hardware hands consecutive blocks of a
+// launch to the 8 XCDs in turn; this remap gives the blocks one XCD receives
+// consecutive items, so elements that share faces are mostly handled on the
+// same XCD and read each other's traces from its L2.  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  constexpr int X = 8;
+  const int q = nb / X, rem = nb - q * X;
+  const int x = b % X, i = b / X;
+  return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + i;
+}
+
 __host__ __device__ inline MeshDims dims_of(const MeshParams& mp) {
   MeshDims d;
   d.ne = mp.ne;

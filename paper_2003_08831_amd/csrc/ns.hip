@@ -227,7 +227,7 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
   const int tid = threadIdx.x;
   const int e = tid / ND;
   const int i = tid - e * ND;
-  const int k = blockIdx.x * E + e;
+  const int k = xcd_block(blockIdx.x, gridDim.x) * E + e;
   const bool valid = e < E && k < mp.ne;
   const long long Ntot = (long long)mp.ne * ND;
   const T gg = T(mp.gg), Tmu = T(mu), Tk = T(kappa), TR = T(R);
@@ -348,7 +348,7 @@ __global__ void __launch_bounds__((NsGeo<DIM, N>::THREADS))
   const int tid = threadIdx.x;
   const int e = tid / ND;
   const int i = tid - e * ND;
-  const int k = blockIdx.x * E + e;
+  const int k = xcd_block(blockIdx.x, gridDim.x) * E + e;
   const bool valid = e < E && k < mp.ne;
   const long long Ntot = (long long)mp.ne * ND;
   int im[3] = {0, 0, 0};

@@ -645,7 +645,10 @@ __global__ void __launch_bounds__((RhsShape<DIM, N, T, RhsCfg<DIM, N, T>::E>::TH
   __shared__ MeshDims smd;
   if (threadIdx.x == 0) smd = dims_of(mp);
   __syncthreads();
-  rhs_block<DIM, N, T, E>(mp, smd, a, blockIdx.x * E, sbuf, sbuf, sred, &s_dt, snbr);
+  // FP32 flux: XCD-contiguous elements (measured 1.5 % faster on 16^3 p3 and
+  // 6 % on 32^3 p3); FP64: launch order (the remap measured 1-2 % slower)
+  const int blk = sizeof(T) == 4 ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  rhs_block<DIM, N, T, E>(mp, smd, a, blk * E, sbuf, sbuf, sred, &s_dt, snbr);
 }
 
 // Batched form: the blocks walk a work list of (simulation, first element)
